@@ -1,0 +1,201 @@
+"""Benchmark: Ozaki-scheme canonical purification on one MI355X.
+
+One step = one complete purification (initial guess to converged P and E) of
+the 16x16x8 tight-binding Hamiltonian (n = 8192, nocc = 2048, tol 1e-8 Ha),
+with H resident in HBM before the timed region starts.  Prints one JSON line:
+value = FP64-equivalent TFLOP/s = iterations * 2 products * 2 n^3 / time.
+
+Beside it: native FP64 purification (rocBLAS DGEMM, same driver) on the same
+GPU, the roofline of the dominant kernel (the INT8 slice-pair GEMM, timed with
+HIP events inside the library on the launch stream), the accuracy against the
+stored oracle samples, and the oracle itself timed on the host on a bounded
+sample (two FP64 iterations with numpy).
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+INT8_PEAK_TOPS = 5000.0      # MI355X dense INT8 MFMA, TOP/s
+FP16_PEAK_TFLOPS = 2500.0    # MI355X dense FP16 MFMA
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 (vector and matrix)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--slices", type=int, default=7)
+    ap.add_argument("--kind", default="int8", choices=["int8", "fp16"])
+    ap.add_argument("--workload", default="tb_8192")
+    ap.add_argument("--native-steps", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-native", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(h, nocc, iters=2):
+    """Oracle FP64 purification (numpy) on the host, `iters` iterations."""
+    from oracle import canonical
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    r = canonical.purify(h, nocc, tol=0.0, max_iter=iters)
+    dt = time.perf_counter() - t0
+    n = h.shape[0]
+    flops = r["iters"] * 2 * 2.0 * n ** 3
+    return dict(value=flops / dt / 1e12, unit="TFLOP/s (FP64-equivalent)", cores=int(threads),
+                kind="oracle",
+                sample=f"{r['iters']} canonical-purification iterations (initial guess + "
+                       f"{2 * r['iters']} FP64 numpy products) of the n={n} workload, "
+                       f"{dt:.1f} s")
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU "
+                                   "sharding is described in DESIGN.md but not built"}))
+        sys.exit(2)
+    import torch
+    import paper_2407_13299_amd as dmp
+    from paper_2407_13299_amd import _lib
+    from paper_2407_13299_amd.workloads import workload
+
+    lib = _lib.load()
+    w = workload(a.workload)
+    h_host, nocc, tol = w["H"], w["nocc"], w["tol"]
+    n = h_host.shape[0]
+    H = torch.from_numpy(h_host).cuda()
+    P = torch.empty_like(H)
+    kind_id = _lib.KINDS[a.kind]
+    ws = torch.empty(lib.dmp_purify_workspace_bytes(n, a.slices, kind_id), dtype=torch.uint8,
+                     device="cuda")
+
+    def run(kind, slices, out, wsb):
+        return dmp.purify(H, nocc, tol=tol, slices=slices, kind=kind, out=out, workspace=wsb)
+
+    print(f"# workload {a.workload}: n={n} nocc={nocc}; warmup {a.warmup}", file=sys.stderr,
+          flush=True)
+    for _ in range(a.warmup):
+        run(a.kind, a.slices, P, ws)
+    torch.cuda.synchronize()
+    lib.dmp_timing_enable(1)
+    lib.dmp_timing_reset()
+    times, iters = [], []
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for k in range(a.steps):
+        t0 = time.perf_counter()
+        _, e, info = run(a.kind, a.slices, P, ws)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        iters.append(info["iters"])
+        print(f"# step {k}: {times[-1] * 1e3:.1f} ms, {info['iters']} iterations, "
+              f"stop={info['stop']}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_all
+    lib.dmp_timing_enable(0)
+    ms_k = [ctypes.c_double(), ctypes.c_double()]
+    nl = [ctypes.c_longlong(), ctypes.c_longlong()]
+    ops = [ctypes.c_double(), ctypes.c_double()]
+    for i in range(2):
+        lib.dmp_timing_read(i, ctypes.byref(ms_k[i]), ctypes.byref(nl[i]), ctypes.byref(ops[i]))
+    ms_per_step = total / a.steps * 1e3
+    it = iters[-1]
+    fp64_eq = it * 2 * 2.0 * n ** 3
+    value = fp64_eq / (ms_per_step / 1e3) / 1e12
+
+    # accuracy against the stored oracle samples
+    acc = {}
+    gpath = os.path.join(ROOT, "tests", "golden", "tb8192_reference.npz")
+    if a.workload == "tb_8192" and os.path.exists(gpath):
+        ref = np.load(gpath)
+        samp = P[torch.from_numpy(ref["si"]).cuda(), torch.from_numpy(ref["sj"]).cuda()].cpu().numpy()
+        rows = P[torch.from_numpy(ref["rows"]).cuda()].cpu().numpy()
+        acc = dict(max_dP_sampled=float(max(np.max(np.abs(samp - ref["P_samples"])),
+                                            np.max(np.abs(rows - ref["P_rows"])))),
+                   dE=float(abs(e - float(ref["E"]))))
+
+    # roofline of the dominant kernel: the update GEMM (X2 P), and the square
+    kernels = {}
+    for i, name in enumerate(("square", "update")):
+        if nl[i].value:
+            avg_ms = ms_k[i].value / nl[i].value
+            per_launch = ops[i].value / nl[i].value
+            kernels[name] = dict(avg_ms=avg_ms, launches=nl[i].value,
+                                 tops=per_launch / (avg_ms / 1e3) / 1e12)
+    dom = kernels.get("update") or kernels.get("square") or {}
+    peak = INT8_PEAK_TOPS if a.kind == "int8" else FP16_PEAK_TFLOPS
+    achieved = dom.get("tops", 0.0)
+    gemm_share = (ms_k[0].value + ms_k[1].value) / (total * 1e3) if total > 0 else 0.0
+
+    native = None
+    if not a.no_native:
+        wsn = torch.empty(lib.dmp_purify_workspace_bytes(n, 0, 0), dtype=torch.uint8, device="cuda")
+        Pn = torch.empty_like(H)
+        run("native", 0, Pn, wsn)     # warm-up (rocBLAS kernel load)
+        torch.cuda.synchronize()
+        tn = []
+        for _ in range(a.native_steps):
+            t0 = time.perf_counter()
+            _, en, infon = run("native", 0, Pn, wsn)
+            torch.cuda.synchronize()
+            tn.append(time.perf_counter() - t0)
+        ms_n = float(np.median(tn)) * 1e3
+        native = dict(ms_per_purification=ms_n, iters=infon["iters"],
+                      tflops_fp64_equiv=infon["iters"] * 4.0 * n ** 3 / (ms_n / 1e3) / 1e12,
+                      frac_of_fp64_peak=(infon["iters"] * 4.0 * n ** 3 / (ms_n / 1e3) / 1e12)
+                      / FP64_PEAK_TFLOPS,
+                      speedup_ozaki_vs_native=ms_n / ms_per_step,
+                      max_dP_ozaki_vs_native=float(torch.max(torch.abs(P - Pn)).item()))
+        del wsn, Pn
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(h_host, nocc)
+
+    line = {
+        "metric": "purification time & FP64-equiv TFLOP/s, Ozaki vs native DGEMM, n=8192, <=1e-10",
+        "value": value,
+        "unit": "TFLOP/s (FP64-equivalent)",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i8" if a.kind == "int8" else "f16",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "n": n, "nocc": nocc, "tol": tol,
+                   "kind": a.kind, "slices": a.slices, "iterations": it,
+                   "products": 2 * it, "slice_products_per_product": a.slices * (a.slices + 1) // 2,
+                   "gemm_time_share": gemm_share, **acc},
+        "roofline": {"bound": "mfma", "kernel": "k_ozgemm (update: X2 P, upper triangle)",
+                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "ops": "int8 multiply-adds counted as 2 ops" if a.kind == "int8" else "fp16",
+                     "frac": achieved / peak if peak else None, "traffic": None,
+                     "kernels": kernels},
+        "native_fp64": native,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,221 @@
+"""Python binding of libdmp: the C-ABI entry points with torch tensors for
+device memory and streams.  Every step of the computation runs in the HIP
+library; this module only allocates outputs/workspace and marshals pointers.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+
+__all__ = ["ozaki_gemm", "ozaki_gemm_batched", "purify", "purify_batched",
+           "autotune_slices", "Purify", "PurifyTape", "max_slices", "version"]
+
+
+def _kind(kind) -> int:
+    if isinstance(kind, int):
+        return kind
+    try:
+        return _lib.KINDS[kind]
+    except KeyError as e:
+        raise ValueError(f"kind must be one of {sorted(_lib.KINDS)}") from e
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check_matrix(t, name):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float64 CUDA (HIP) tensor")
+    if t.dim() != 2 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous 2-D tensor")
+
+
+def _workspace(nbytes: int, device):
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def version() -> str:
+    return _lib.load().dmp_version().decode()
+
+
+def max_slices(kind="int8") -> int:
+    return _lib.load().dmp_max_slices(_kind(kind))
+
+
+def ozaki_gemm(A, B, slices=7, kind="int8", trans_a=False, trans_b=False, out=None,
+               stream=None):
+    """C = op(A) op(B) by the Ozaki scheme (or rocBLAS DGEMM for kind='native')."""
+    lib = _lib.load()
+    _check_matrix(A, "A")
+    _check_matrix(B, "B")
+    m = A.shape[1] if trans_a else A.shape[0]
+    k = A.shape[0] if trans_a else A.shape[1]
+    kb = B.shape[1] if trans_b else B.shape[0]
+    n = B.shape[0] if trans_b else B.shape[1]
+    if k != kb:
+        raise ValueError(f"inner dimensions differ: {k} vs {kb}")
+    if out is None:
+        out = torch.empty((m, n), dtype=torch.float64, device=A.device)
+    else:
+        _check_matrix(out, "out")
+    kd = _kind(kind)
+    ws = _workspace(lib.dmp_gemm_workspace_bytes(m, n, k, slices, kd), A.device)
+    st = lib.dmp_ozaki_gemm(b"T" if trans_a else b"N", b"T" if trans_b else b"N", m, n, k,
+                            _ptr(A), max(1, A.shape[1]), _ptr(B), max(1, B.shape[1]),
+                            _ptr(out), max(1, out.shape[1]), slices, kd, _ptr(ws), ws.numel(),
+                            _stream(stream))
+    _lib.check(st, "dmp_ozaki_gemm")
+    return out
+
+
+def ozaki_gemm_batched(As, Bs, slices=7, kind="int8", stream=None):
+    """C_b = A_b B_b for lists of matrices, one grouped launch per phase."""
+    lib = _lib.load()
+    cnt = len(As)
+    if len(Bs) != cnt:
+        raise ValueError("As and Bs differ in length")
+    for a, b in zip(As, Bs):
+        _check_matrix(a, "A")
+        _check_matrix(b, "B")
+        if a.shape[1] != b.shape[0]:
+            raise ValueError("inner dimensions differ")
+    Cs = [torch.empty((a.shape[0], b.shape[1]), dtype=torch.float64, device=a.device)
+          for a, b in zip(As, Bs)]
+    IA = ctypes.c_int * cnt
+    PA = ctypes.c_void_p * cnt
+    m = IA(*[a.shape[0] for a in As])
+    n = IA(*[b.shape[1] for b in Bs])
+    k = IA(*[a.shape[1] for a in As])
+    kd = _kind(kind)
+    ws = _workspace(lib.dmp_gemm_batched_workspace_bytes(cnt, m, n, k, slices, kd), As[0].device)
+    st = lib.dmp_ozaki_gemm_batched(cnt, m, n, k, PA(*[a.data_ptr() for a in As]),
+                                    PA(*[b.data_ptr() for b in Bs]),
+                                    PA(*[c.data_ptr() for c in Cs]), slices, kd, _ptr(ws),
+                                    ws.numel(), _stream(stream))
+    _lib.check(st, "dmp_ozaki_gemm_batched")
+    return Cs
+
+
+def purify(H, nocc, tol=1e-8, slices=7, kind="int8", max_iter=200, out=None, stream=None,
+           workspace=None):
+    """Canonical purification; returns (P, E, info dict)."""
+    lib = _lib.load()
+    _check_matrix(H, "H")
+    n = H.shape[0]
+    if H.shape[1] != n:
+        raise ValueError("H must be square")
+    P = out if out is not None else torch.empty_like(H)
+    kd = _kind(kind)
+    need = lib.dmp_purify_workspace_bytes(n, slices, kd)
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, H.device)
+    e = ctypes.c_double(0.0)
+    info = _lib.DmpInfo()
+    st = lib.dmp_purify(_ptr(H), n, int(nocc), float(tol), int(slices), kd, int(max_iter),
+                        _ptr(P), ctypes.byref(e), ctypes.byref(info), _ptr(ws), ws.numel(),
+                        _stream(stream))
+    _lib.check(st, "dmp_purify")
+    return P, e.value, info.as_dict()
+
+
+def purify_batched(Hs, noccs, tol=1e-8, slices=0, kind="int8", max_iter=200, stream=None):
+    """Purify a list of Hamiltonians together; slices <= 0 uses the tuned table.
+
+    Returns (list of P, list of E, list of info dicts)."""
+    lib = _lib.load()
+    cnt = len(Hs)
+    for h in Hs:
+        _check_matrix(h, "H")
+    Ps = [torch.empty_like(h) for h in Hs]
+    IA = ctypes.c_int * cnt
+    PA = ctypes.c_void_p * cnt
+    n = IA(*[h.shape[0] for h in Hs])
+    nocc = IA(*[int(x) for x in noccs])
+    kd = _kind(kind)
+    ws = _workspace(lib.dmp_purify_batched_workspace_bytes(cnt, n, int(slices), kd), Hs[0].device)
+    E = (ctypes.c_double * cnt)()
+    infos = (_lib.DmpInfo * cnt)()
+    st = lib.dmp_purify_batched(cnt, PA(*[h.data_ptr() for h in Hs]), n, nocc, float(tol),
+                                int(slices), kd, int(max_iter), PA(*[p.data_ptr() for p in Ps]),
+                                E, infos, _ptr(ws), ws.numel(), _stream(stream))
+    _lib.check(st, "dmp_purify_batched")
+    return Ps, list(E), [i.as_dict() for i in infos]
+
+
+def autotune_slices(n, target=1e-10, kind="int8") -> int:
+    return _lib.load().dmp_autotune_slices(int(n), float(target), _kind(kind))
+
+
+class PurifyTape:
+    """Owner of a forward tape (iterates checkpointed every ``stride`` steps)."""
+
+    def __init__(self, H, nocc, tol=1e-8, slices=7, kind="int8", max_iter=200, stride=0,
+                 stream=None):
+        lib = _lib.load()
+        _check_matrix(H, "H")
+        n = H.shape[0]
+        self.n = n
+        self.device = H.device
+        self.P = torch.empty_like(H)
+        e = ctypes.c_double(0.0)
+        info = _lib.DmpInfo()
+        tape = ctypes.c_void_p()
+        st = lib.dmp_purify_fwd_tape(_ptr(H), n, int(nocc), float(tol), int(slices), _kind(kind),
+                                     int(max_iter), int(stride), _ptr(self.P), ctypes.byref(e),
+                                     ctypes.byref(info), ctypes.byref(tape), _stream(stream))
+        _lib.check(st, "dmp_purify_fwd_tape")
+        self._tape = tape
+        self.E = e.value
+        self.info = info.as_dict()
+
+    def branches(self):
+        lib = _lib.load()
+        it = ctypes.c_int(0)
+        lib.dmp_tape_info(self._tape, ctypes.byref(it), None)
+        br = (ctypes.c_int * max(1, it.value))()
+        lib.dmp_tape_info(self._tape, ctypes.byref(it), br)
+        return list(br)[: it.value]
+
+    def backward(self, Pbar, stream=None):
+        lib = _lib.load()
+        _check_matrix(Pbar, "Pbar")
+        Pbar = 0.5 * (Pbar + Pbar.T)
+        Pbar = Pbar.contiguous()
+        Hbar = torch.empty_like(Pbar)
+        ws = _workspace(lib.dmp_purify_bwd_workspace_bytes(self._tape), self.device)
+        st = lib.dmp_purify_bwd(self._tape, _ptr(Pbar), _ptr(Hbar), _ptr(ws), ws.numel(),
+                                _stream(stream))
+        _lib.check(st, "dmp_purify_bwd")
+        return Hbar
+
+    def __del__(self):
+        t = getattr(self, "_tape", None)
+        if t is not None and t.value:
+            try:
+                _lib.load().dmp_tape_free(t)
+            except Exception:
+                pass
+            self._tape = None
+
+
+class Purify(torch.autograd.Function):
+    """P = purify(H) with a hand-written adjoint: backward returns dL/dH."""
+
+    @staticmethod
+    def forward(ctx, H, nocc, tol=1e-8, slices=7, kind="int8", max_iter=200, stride=0):
+        tape = PurifyTape(H, nocc, tol, slices, kind, max_iter, stride)
+        ctx.tape = tape
+        return tape.P.clone()
+
+    @staticmethod
+    def backward(ctx, grad_p):
+        hbar = ctx.tape.backward(grad_p.contiguous())
+        return hbar, None, None, None, None, None, None

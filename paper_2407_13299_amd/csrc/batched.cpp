@@ -1,0 +1,69 @@
+// Batched purification entry point and the slice-count table.
+#include <cmath>
+#include <vector>
+
+#include "host.hpp"
+#include "tuned_table.h"
+
+using namespace dmp;
+
+extern "C" {
+
+int dmp_autotune_slices(int n, double target, dmp_kind kind) {
+    if (kind == DMP_FP64_NATIVE) return 0;
+    if (n < 1 || !(target > 0.0)) return kMaxSlices;
+    // error model max|dP| ~ C n^a 2^-(8S - 1), with (C, a) measured per kind
+    const double c = kind == DMP_OZ_FP16 ? kTunedErrC[1] : kTunedErrC[0];
+    const double a = kind == DMP_OZ_FP16 ? kTunedErrA[1] : kTunedErrA[0];
+    for (int s = 1; s <= kMaxSlices; ++s) {
+        const double err = c * std::pow(double(n), a) * std::ldexp(1.0, -(8 * s - 1));
+        if (err <= target && n <= max_k_for_slices(s)) return s;
+    }
+    return kMaxSlices;
+}
+
+size_t dmp_purify_batched_workspace_bytes(int count, const int* n, int slices, dmp_kind kind) {
+    if (count < 1 || !n) return 0;
+    std::vector<int> s(count);
+    for (int b = 0; b < count; ++b) {
+        if (n[b] < 1) return 0;
+        s[b] = slices > 0 ? slices : dmp_autotune_slices(n[b], kTunedTarget, kind);
+    }
+    std::vector<const double*> h(count, nullptr);
+    std::vector<double*> p(count, nullptr);
+    std::vector<int> nocc(count, 0);
+    size_t need = 0;
+    purify_many(count, h.data(), n, nocc.data(), 1.0, s.data(), kind, 1, p.data(), nullptr,
+                nullptr, nullptr, 0, nullptr, &need);
+    return need;
+}
+
+int dmp_purify_batched(int count, const double* const* H, const int* n, const int* nocc,
+                       double tol, int slices, dmp_kind kind, int max_iter, double* const* P,
+                       double* E, dmp_info* info, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    if (count < 1 || !H || !n || !nocc || !P || !E) {
+        set_error("bad batch arguments");
+        return DMP_EINVAL;
+    }
+    std::vector<int> s(count);
+    for (int b = 0; b < count; ++b) {
+        DMP_CHECK(validate_purify_args(H[b], n[b], nocc[b], tol, max_iter, P[b]));
+        s[b] = kind == DMP_FP64_NATIVE ? 0 : (slices > 0 ? slices : dmp_autotune_slices(n[b], kTunedTarget, kind));
+        if (kind != DMP_FP64_NATIVE) {
+            DMP_CHECK(check_kind_slices(kind, s[b]));
+            if (n[b] > max_k_for_slices(s[b])) {
+                set_error("matrix %d: n = %d exceeds the exact INT32 range for %d slices", b, n[b], s[b]);
+                return DMP_EINVAL;
+            }
+        }
+    }
+    if (ws == nullptr) {
+        set_error("workspace required");
+        return DMP_ENOMEM;
+    }
+    return purify_many(count, H, n, nocc, tol, s.data(), kind, max_iter, P, E, info, ws, ws_bytes,
+                       static_cast<hipStream_t>(stream), nullptr);
+}
+
+}  // extern "C"

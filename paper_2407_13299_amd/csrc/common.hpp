@@ -1,0 +1,139 @@
+// Internal definitions shared by the HIP translation units of libdmp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "dmp.h"
+
+namespace dmp {
+
+// ---- error reporting ------------------------------------------------------
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define DMP_CHECK_HIP(call)                                                  \
+    do {                                                                     \
+        hipError_t err_ = (call);                                            \
+        if (err_ != hipSuccess) {                                            \
+            ::dmp::set_error("%s:%d %s: %s", __FILE__, __LINE__, #call,       \
+                             hipGetErrorString(err_));                       \
+            return DMP_EHIP;                                                 \
+        }                                                                    \
+    } while (0)
+
+#define DMP_CHECK(expr)                                                      \
+    do {                                                                     \
+        int st_ = (expr);                                                    \
+        if (st_ < 0) return st_;                                             \
+    } while (0)
+
+// ---- Ozaki split geometry -------------------------------------------------
+// Digit planes are stored in "fragment blocks": 32 rows x CK reduction
+// elements, 1 KiB each, laid out exactly as the 32x32 MFMA operand registers
+// of one wavefront (lane l holds row l % 32 and 16 bytes of consecutive
+// reduction index starting at (l / 32) * CK / 2).  For every (row block,
+// chunk) the S planes are adjacent, so one chunk of one 32-row block is a
+// single contiguous S KiB run.
+//   INT8: CK = 32 (one v_mfma_i32_32x32x32_i8 per slice pair and chunk)
+//   FP16: CK = 16 (one v_mfma_f32_32x32x16_f16 per slice pair and chunk)
+constexpr int kFragRows = 32;
+constexpr int kFragBytes = 1024;
+constexpr int kTile = 64;            // GEMM output tile (2 x 2 fragments)
+constexpr int kPad = 64;             // row / reduction padding of the planes
+constexpr int kMaxSlices = 12;
+constexpr int kTopBits = 6;          // fractional bits of the first digit
+constexpr int kDigitBits = 8;        // bits of every further digit
+// Exponent recorded for a row (column) holding a NaN or an infinity; the
+// products of such a row come out NaN.
+constexpr int kNonFiniteExp = 1 << 20;
+
+inline int chunk_k(dmp_kind kind) { return kind == DMP_OZ_FP16 ? 16 : 32; }
+__host__ __device__ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Largest reduction length whose INT32 group sums cannot overflow:
+// (g - 1) k 2^14 < 2^31 for every group g <= S + 1.
+inline int64_t max_k_for_slices(int s) { return ((1ll << 31) - 1) / (int64_t(s) * 16384); }
+
+// Bytes of the digit planes of an R x K operand.
+inline size_t plane_bytes(int64_t r, int64_t k, int s, dmp_kind kind) {
+    return size_t(round_up(r, kPad)) * size_t(round_up(k, kPad)) * size_t(s) *
+           (kind == DMP_OZ_FP16 ? 2 : 1);
+}
+
+// One output tile of a (possibly grouped) GEMM: 64 x 64 block (I, J) of
+// matrix ``mat`` of a batch.
+struct Tile {
+    uint16_t I, J;
+    uint32_t mat;
+};
+
+// Per-matrix descriptor of a grouped purification / GEMM, in device memory.
+struct MatDesc {
+    const uint8_t* pa;     // digit planes of the left operand (rows)
+    const uint8_t* pb;     // digit planes of the right operand (columns)
+    const int* ea;         // row exponents of the left operand
+    const int* eb;         // column exponents of the right operand
+    const double* P;       // current iterate
+    const double* X2;      // square of the iterate
+    const double* H;       // Hamiltonian
+    double* out;           // output matrix
+    double* out2;          // second output (mirror target / spare)
+    int64_t a_rb_stride;   // bytes between 32-row blocks of pa
+    int64_t b_rb_stride;   // bytes between 32-row blocks of pb
+    int M, N, KC;          // rows, columns, reduction chunks
+    int ldc;
+    int state_index;       // index of the matrix's DevState
+    int pad_;
+};
+
+// Device-side purification state of one matrix (host-readable copy).
+struct DevState {
+    double h_min, h_max, trace_h, mu, lambda, theta;
+    double c, alpha, beta, gamma, t1, t2;
+    double E, E_prev, dE, dE_prev, trace_p, tol;
+    int iters, done, stop_reason, branch;
+    int max_iter, nonfinite, n, nocc;
+    int clamped, pad_[3];
+};
+
+// One operand to split (single launch: passed by value; grouped launch: an
+// array in device memory, blocks mapped to matrices by the first-unit
+// fields).
+struct SplitDesc {
+    const double* A;    // source matrix, row-major
+    int64_t lda;
+    int R, K;           // rows / reduction length of the operand
+    int trans;          // 0: operand row r is A[r, :]; 1: operand row r is A[:, r]
+    int KC;             // chunks along the reduction (padded K / CK)
+    uint64_t* maxbits;  // [Rp] bit pattern of max |row|
+    int* expo;          // [Rp] exponents
+    uint8_t* planes;    // digit planes
+    int ub_rowmax;      // first k_rowmax unit of this matrix (grouped)
+    int ub_digits;      // first k_digits unit of this matrix (grouped)
+    int state_index;    // -1: no state
+    int pad_;
+};
+
+// Epilogue modes of the slice GEMM.
+enum EpiMode : int {
+    EPI_STORE = 0,     // C = A B (general, full tiles)
+    EPI_SQUARE = 1,    // X2 = P P (upper tiles, mirrored) + traces for c
+    EPI_UPDATE = 2,    // P' = a P + b X2 + g X2 P (upper, mirrored) + E, tr
+};
+
+constexpr int kPartials = 2;   // partial sums written per tile
+
+// Arguments of one slice-GEMM launch.
+struct GemmParams {
+    const Tile* tiles;
+    const MatDesc* descs;   // grouped launch (device); nullptr: use ``one``
+    MatDesc one;
+    double* partials;       // [tiles][kPartials] (purification modes)
+    const DevState* states; // nullable; tiles of finished matrices exit
+    int mode;
+};
+
+}  // namespace dmp

@@ -1,0 +1,127 @@
+// Host-side helpers of libdmp: error text, tile orders, rocBLAS handles.
+#include "host.hpp"
+
+#include <cstdarg>
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+namespace dmp {
+
+static thread_local char g_error[512] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_error, sizeof(g_error), fmt, ap);
+    va_end(ap);
+}
+
+void clear_error() { g_error[0] = '\0'; }
+
+void append_tiles(std::vector<Tile>& out, int tm, int tn, bool upper, uint32_t mat) {
+    constexpr int G = 8;
+    const int sm = (tm + G - 1) / G, sn = (tn + G - 1) / G;
+    for (int si = 0; si < sm; ++si)
+        for (int sj = upper ? si : 0; sj < sn; ++sj)
+            for (int i = si * G; i < std::min(tm, si * G + G); ++i)
+                for (int j = sj * G; j < std::min(tn, sj * G + G); ++j) {
+                    if (upper && j < i) continue;
+                    out.push_back(Tile{uint16_t(i), uint16_t(j), mat});
+                }
+}
+
+int cached_tiles(int tm, int tn, bool upper, const Tile** out) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, bool>, Tile*> cache;
+    int dev = 0;
+    DMP_CHECK_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    auto key = std::make_tuple(dev, tm, tn, upper);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+        *out = it->second;
+        return DMP_OK;
+    }
+    std::vector<Tile> host;
+    append_tiles(host, tm, tn, upper, 0);
+    Tile* devp = nullptr;
+    DMP_CHECK_HIP(hipMalloc(&devp, std::max<size_t>(1, host.size()) * sizeof(Tile)));
+    if (!host.empty())
+        DMP_CHECK_HIP(hipMemcpy(devp, host.data(), host.size() * sizeof(Tile), hipMemcpyHostToDevice));
+    cache[key] = devp;
+    *out = devp;
+    return DMP_OK;
+}
+
+int blas_handle(hipStream_t stream, rocblas_handle* out) {
+    static std::mutex mu;
+    static std::map<int, rocblas_handle> handles;
+    int dev = 0;
+    DMP_CHECK_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = handles.find(dev);
+    rocblas_handle h;
+    if (it == handles.end()) {
+        if (rocblas_create_handle(&h) != rocblas_status_success) {
+            set_error("rocblas_create_handle failed");
+            return DMP_EHIP;
+        }
+        handles[dev] = h;
+    } else {
+        h = it->second;
+    }
+    if (rocblas_set_stream(h, stream) != rocblas_status_success) {
+        set_error("rocblas_set_stream failed");
+        return DMP_EHIP;
+    }
+    *out = h;
+    return DMP_OK;
+}
+
+// Row-major C = op(A) op(B) through column-major rocBLAS: the row-major
+// matrices are the transposes of the column-major views, so compute
+// C^T = op(B)^T op(A)^T.
+int native_dgemm(hipStream_t stream, bool ta, bool tb, int m, int n, int k, const double* A,
+                 int lda, const double* B, int ldb, double* C, int ldc) {
+    rocblas_handle h;
+    DMP_CHECK(blas_handle(stream, &h));
+    const double one = 1.0, zero = 0.0;
+    rocblas_status s = rocblas_dgemm(h, tb ? rocblas_operation_transpose : rocblas_operation_none,
+                                     ta ? rocblas_operation_transpose : rocblas_operation_none, n,
+                                     m, k, &one, B, ldb, A, lda, &zero, C, ldc);
+    if (s != rocblas_status_success) {
+        set_error("rocblas_dgemm failed (%d)", int(s));
+        return DMP_EHIP;
+    }
+    return DMP_OK;
+}
+
+int check_kind_slices(dmp_kind kind, int slices) {
+    if (kind != DMP_OZ_INT8 && kind != DMP_OZ_FP16 && kind != DMP_FP64_NATIVE) {
+        set_error("unknown kind %d", int(kind));
+        return DMP_EINVAL;
+    }
+    if (kind != DMP_FP64_NATIVE && (slices < 1 || slices > kMaxSlices)) {
+        set_error("slices must lie in [1, %d], got %d", kMaxSlices, slices);
+        return DMP_EINVAL;
+    }
+    return DMP_OK;
+}
+
+int64_t chunks_of(int k, dmp_kind kind) { return round_up(k, kPad) / chunk_k(kind); }
+
+}  // namespace dmp
+
+extern "C" {
+
+const char* dmp_last_error(void) { return dmp::g_error; }
+
+const char* dmp_version(void) { return "dmp 0.1 (gfx950)"; }
+
+int dmp_max_slices(dmp_kind kind) {
+    return (kind == DMP_OZ_INT8 || kind == DMP_OZ_FP16) ? dmp::kMaxSlices : 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,67 @@
+// Host-side helpers of libdmp (no device code).
+#pragma once
+
+#include <rocblas/rocblas.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "common.hpp"
+
+namespace dmp {
+
+// Carves 256-byte-aligned regions out of a workspace; with base == nullptr it
+// only measures.
+class Carver {
+public:
+    explicit Carver(void* base) : base_(static_cast<uint8_t*>(base)) {}
+    template <typename T>
+    T* take(size_t count) {
+        off_ = (off_ + 255) & ~size_t(255);
+        T* p = base_ ? reinterpret_cast<T*>(base_ + off_) : nullptr;
+        off_ += count * sizeof(T);
+        return p;
+    }
+    size_t used() const { return (off_ + 255) & ~size_t(255); }
+
+private:
+    uint8_t* base_;
+    size_t off_ = 0;
+};
+
+// Order of the 64 x 64 output tiles of one matrix: 8 x 8 super-tiles,
+// row-major over super-tiles and within each; ``upper`` keeps I <= J only.
+void append_tiles(std::vector<Tile>& out, int tm, int tn, bool upper, uint32_t mat);
+
+// Device copy of the tile order of a single tm x tn product, cached per
+// device for the life of the process.
+int cached_tiles(int tm, int tn, bool upper, const Tile** out);
+
+// rocBLAS handle of the current device (created once), bound to ``stream``.
+int blas_handle(hipStream_t stream, rocblas_handle* out);
+
+// C = A B for row-major n x n ... general: C (m x n) = op(A) op(B).
+int native_dgemm(hipStream_t stream, bool ta, bool tb, int m, int n, int k, const double* A,
+                 int lda, const double* B, int ldb, double* C, int ldc);
+
+int launch_split(const SplitDesc& d, int S, dmp_kind kind, const DevState* st, hipStream_t s);
+int launch_split_grouped_rowmax(const SplitDesc* descs_dev, int count, int units,
+                                const DevState* st, hipStream_t stream);
+int launch_split_grouped_digits(const SplitDesc* descs_dev, int count, int units, int S,
+                                dmp_kind kind, const DevState* st, hipStream_t stream);
+int split_units_rowmax(int R);
+int split_units_digits(int R, int KC);
+
+struct GemmParams;
+int launch_ozgemm(int S, dmp_kind kind, const GemmParams& p, int ntiles, hipStream_t stream);
+
+int check_kind_slices(dmp_kind kind, int slices);
+int validate_purify_args(const double* H, int n, int nocc, double tol, int max_iter,
+                         const double* P);
+int purify_many(int count, const double* const* H, const int* n, const int* nocc, double tol,
+                const int* slices, dmp_kind kind, int max_iter, double* const* P, double* E,
+                dmp_info* info, void* ws, size_t ws_bytes, hipStream_t s, size_t* need_out);
+int64_t chunks_of(int k, dmp_kind kind);
+
+}  // namespace dmp

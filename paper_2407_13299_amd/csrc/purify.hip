@@ -1,0 +1,919 @@
+// Canonical density-matrix purification driven by Ozaki-scheme products
+// (Sec. 2.3 and 2.4; canonical trace-conserving form cited in Sec. 1).
+//
+// Per iteration and per matrix (every phase is one launch over all matrices
+// of a group; matrices that have stopped skip their blocks):
+//   split(P)            row exponents + digit planes of P (serve as both
+//                       operands: P is exactly symmetric)
+//   gemm SQUARE         X2 = P P, partial traces
+//   finalize_coef       t1 = tr(P - X2), t2 = tr(X2 - P^3), c, branch,
+//                       (alpha, beta, gamma)
+//   split(X2)
+//   gemm UPDATE         P' = alpha P + beta X2 + gamma X2 P, partial tr(P'H)
+//   finalize_iter       E, dE, stopping rule
+// All reductions are fixed-order (no floating-point atomics), so runs are
+// bitwise reproducible.  FP64 everywhere except the slice products (Sec. 4).
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "host.hpp"
+
+namespace dmp {
+
+constexpr int kE0Blocks = 256;          // fixed grid of the P0 / energy pass
+
+// Kernel-timing instrumentation (see dmp_timing_*).
+struct TimingState {
+    bool on = false;
+    double ms[2] = {0.0, 0.0};
+    long long launches[2] = {0, 0};
+    double ops[2] = {0.0, 0.0};
+};
+static TimingState g_timing;
+
+struct PendingTimer {
+    hipEvent_t start, stop;
+    int which;
+    double ops;
+};
+constexpr double kStagnationWindow = 1e-2;
+
+// Per-matrix arguments of the small purification kernels.
+struct PurDesc {
+    const double* H;
+    double* Pb[2];          // ping-pong iterates; Pb[0] is the caller's P
+    double* X2;             // square (Ozaki) / X2 (native)
+    double* X3;             // native only: X2 P
+    double* rows;           // [3 n]: Gershgorin low, high, diagonal per row
+    int* rowbad;            // [n]: non-finite flag per row
+    double* e0;             // [kE0Blocks] partial energies of P0
+    double* partials;       // [(tile or block) count][kPartials]
+    int n, nocc;
+    int part_begin, part_end;   // partial range of this matrix
+};
+
+__device__ inline double wsum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Fixed-order block sum of 256 values (one per thread).
+__device__ inline double block_sum(double v, double* sh) {
+    v = wsum(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+    __syncthreads();
+    return r;
+}
+
+__device__ inline double block_min(double v, double* sh) {
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = fmin(fmin(sh[0], sh[1]), fmin(sh[2], sh[3]));
+    __syncthreads();
+    return r;
+}
+
+__device__ inline double block_max(double v, double* sh) {
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    __syncthreads();
+    return r;
+}
+
+// Gershgorin discs per row: centre H_ii, radius sum_{j != i} |H_ij|; one
+// wavefront per row, grid.y = matrix.
+__global__ __launch_bounds__(256) void k_gershgorin(const PurDesc* pd) {
+    const PurDesc& d = pd[blockIdx.y];
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (r >= d.n) return;
+    const double* row = d.H + int64_t(r) * d.n;
+    double s = 0.0;
+    int bad = 0;
+    for (int j = lane; j < d.n; j += 64) {
+        const double v = row[j];
+        bad |= !isfinite(v);
+        s += fabs(v);
+    }
+    s = wsum(s);
+    for (int off = 32; off > 0; off >>= 1) bad |= __shfl_xor(bad, off, 64);
+    if (lane == 0) {
+        const double dg = row[r];
+        const double rad = s - fabs(dg);
+        d.rows[r] = dg - rad;
+        d.rows[d.n + r] = dg + rad;
+        d.rows[2 * d.n + r] = dg;
+        d.rowbad[r] = bad;
+    }
+}
+
+// Bounds, trace and the canonical initial-guess scalars; one block per matrix.
+__global__ __launch_bounds__(256) void k_finalize_init(const PurDesc* pd, DevState* states,
+                                                       double tol, int max_iter) {
+    __shared__ double sh[4];
+    const PurDesc& d = pd[blockIdx.x];
+    DevState& s = states[blockIdx.x];
+    const int n = d.n;
+    double lo = INFINITY, hi = -INFINITY, tr = 0.0;
+    int bad = 0;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        lo = fmin(lo, d.rows[i]);
+        hi = fmax(hi, d.rows[n + i]);
+        tr += d.rows[2 * n + i];
+        bad |= d.rowbad[i];
+    }
+    lo = block_min(lo, sh);
+    hi = block_max(hi, sh);
+    tr = block_sum(tr, sh);
+    const double anybad = block_max(double(bad), sh);
+    if (threadIdx.x == 0) {
+        s = DevState{};
+        s.n = n;
+        s.nocc = d.nocc;
+        s.tol = tol;
+        s.max_iter = max_iter;
+        s.h_min = lo;
+        s.h_max = hi;
+        s.trace_h = tr;
+        s.mu = tr / n;
+        s.theta = double(d.nocc) / n;
+        double lam = 0.0;
+        if (d.nocc > 0 && d.nocc < n) {
+            const double a = (hi - s.mu) > 0.0 ? s.theta / (hi - s.mu) : 0.0;
+            const double b = (s.mu - lo) > 0.0 ? (1.0 - s.theta) / (s.mu - lo) : 0.0;
+            lam = fmin(a, b);
+        } else {
+            s.done = 1;   // P = 0 or I exactly, no iterations
+            s.stop_reason = DMP_STOP_CONVERGED;
+        }
+        s.lambda = lam;
+        if (anybad != 0.0) {
+            s.nonfinite = 1;
+            s.done = 1;
+            s.stop_reason = DMP_STOP_NONFINITE;
+        }
+    }
+}
+
+// P0 = lam (mu I - H) + theta I from the upper triangle of H (mirrored), and
+// partial energies tr(P0 H); fixed grid of kE0Blocks blocks per matrix.
+__global__ __launch_bounds__(256) void k_init_p0(const PurDesc* pd, const DevState* states) {
+    __shared__ double sh[4];
+    const PurDesc& d = pd[blockIdx.y];
+    const DevState& s = states[blockIdx.y];
+    const int n = d.n;
+    const int64_t tot = int64_t(n) * n;
+    double e = 0.0;
+    if (!s.nonfinite) {
+        for (int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x; idx < tot;
+             idx += int64_t(kE0Blocks) * 256) {
+            const int i = int(idx / n), j = int(idx % n);
+            const double h = i <= j ? d.H[idx] : d.H[int64_t(j) * n + i];
+            const double p = s.lambda * ((i == j ? s.mu : 0.0) - h) + (i == j ? s.theta : 0.0);
+            d.Pb[0][idx] = p;
+            e += p * h;
+        }
+    }
+    e = block_sum(e, sh);
+    if (threadIdx.x == 0) d.e0[blockIdx.x] = e;
+}
+
+__global__ __launch_bounds__(256) void k_finalize_e0(const PurDesc* pd, DevState* states) {
+    __shared__ double sh[4];
+    const PurDesc& d = pd[blockIdx.x];
+    DevState& s = states[blockIdx.x];
+    double e = 0.0;
+    for (int i = threadIdx.x; i < kE0Blocks; i += 256) e += d.e0[i];
+    e = block_sum(e, sh);
+    if (threadIdx.x == 0) {
+        s.E = e;
+        s.E_prev = e;
+        s.trace_p = double(d.nocc);
+    }
+}
+
+// Fixed-order sum of a matrix's partials, column q.
+__device__ inline double sum_partials(const PurDesc& d, int q, double* sh) {
+    double v = 0.0;
+    for (int i = d.part_begin + threadIdx.x; i < d.part_end; i += 256)
+        v += d.partials[int64_t(i) * kPartials + q];
+    return block_sum(v, sh);
+}
+
+__global__ __launch_bounds__(256) void k_finalize_coef(const PurDesc* pd, DevState* states) {
+    __shared__ double sh[4];
+    const PurDesc& d = pd[blockIdx.x];
+    DevState& s = states[blockIdx.x];
+    if (s.done) return;
+    const double t1 = sum_partials(d, 0, sh);
+    const double t2 = sum_partials(d, 1, sh);
+    if (threadIdx.x == 0) {
+        const double raw = t1 == 0.0 ? 0.5 : t2 / t1;
+        const double c = fmin(fmax(raw, 0.0), 1.0);
+        s.t1 = t1;
+        s.t2 = t2;
+        s.c = c;
+        s.clamped = (t1 == 0.0 || raw != c) ? 1 : 0;
+        if (c >= 0.5) {
+            s.branch = 1;
+            s.alpha = 0.0;
+            s.beta = (1.0 + c) / c;
+            s.gamma = -1.0 / c;
+        } else {
+            s.branch = 0;
+            s.alpha = (1.0 - 2.0 * c) / (1.0 - c);
+            s.beta = (1.0 + c) / (1.0 - c);
+            s.gamma = -1.0 / (1.0 - c);
+        }
+    }
+}
+
+// Energy of the new iterate and the stopping rule of Sec. 3.
+__global__ __launch_bounds__(256) void k_finalize_iter(const PurDesc* pd, DevState* states) {
+    __shared__ double sh[4];
+    const PurDesc& d = pd[blockIdx.x];
+    DevState& s = states[blockIdx.x];
+    if (s.done) return;
+    const double e = sum_partials(d, 0, sh);
+    const double tr = sum_partials(d, 1, sh);
+    if (threadIdx.x == 0) {
+        const double de = e - s.E;
+        s.dE_prev = s.dE;
+        s.dE = de;
+        s.E_prev = s.E;
+        s.E = e;
+        s.trace_p = tr;
+        s.iters += 1;
+        int stop = -1;
+        if (!isfinite(e)) stop = DMP_STOP_NONFINITE;
+        else if (fabs(de) < s.tol) stop = DMP_STOP_CONVERGED;
+        else if (s.iters >= 2 && de > 0.0 && s.dE_prev > 0.0 && fabs(de) < kStagnationWindow)
+            stop = DMP_STOP_STAGNATED;
+        else if (s.iters >= s.max_iter) stop = DMP_STOP_MAX_ITER;
+        if (stop >= 0) {
+            s.done = 1;
+            s.stop_reason = stop;
+        }
+    }
+}
+
+// ---- native FP64 path: elementwise work around rocBLAS products -----------
+
+// Partials of tr(P - X2) and sum_{i<=j} mult X2_ij (delta_ij - P_ij) over the
+// upper triangle (mult 2 off the diagonal), fixed grid.
+__global__ __launch_bounds__(256) void k_native_square(const PurDesc* pd, const DevState* states,
+                                                       int nblocks) {
+    __shared__ double sh[4];
+    const PurDesc& d = pd[0];
+    if (states[0].done) return;
+    const int n = d.n;
+    const double* P = d.Pb[states[0].iters & 1];
+    const int64_t tot = int64_t(n) * n;
+    double s0 = 0.0, s1 = 0.0;
+    for (int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x; idx < tot;
+         idx += int64_t(nblocks) * 256) {
+        const int i = int(idx / n), j = int(idx % n);
+        if (j < i) continue;
+        const double x = d.X2[idx], p = P[idx];
+        if (i == j) {
+            s0 += p - x;
+            s1 += x * (1.0 - p);
+        } else {
+            s1 -= 2.0 * x * p;
+        }
+    }
+    s0 = block_sum(s0, sh);
+    s1 = block_sum(s1, sh);
+    if (threadIdx.x == 0) {
+        d.partials[int64_t(blockIdx.x) * kPartials + 0] = s0;
+        d.partials[int64_t(blockIdx.x) * kPartials + 1] = s1;
+    }
+}
+
+// P' = alpha P + beta X2 + gamma X3 on 32 x 32 tile pairs I <= J, written to
+// (I, J) and, transposed through LDS, to (J, I); partials of tr(P'H), tr P'.
+__global__ __launch_bounds__(256) void k_native_update(const PurDesc* pd, const DevState* states,
+                                                       const int2* pairs) {
+    __shared__ double tileT[32][33];
+    __shared__ double sh[4];
+    const PurDesc& d = pd[0];
+    const DevState& s = states[0];
+    if (s.done) return;
+    const int n = d.n;
+    const double* P = d.Pb[s.iters & 1];
+    double* Pn = d.Pb[(s.iters + 1) & 1];
+    const int2 pr = pairs[blockIdx.x];
+    const int I = pr.x, J = pr.y;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    double se = 0.0, st = 0.0;
+    for (int r = ty; r < 32; r += 8) {
+        const int i = I * 32 + r, j = J * 32 + tx;
+        double v = 0.0;
+        if (i < n && j < n && !(I == J && j < i)) {
+            const int64_t ij = int64_t(i) * n + j;
+            v = s.alpha * P[ij] + s.beta * d.X2[ij] + s.gamma * d.X3[ij];
+            Pn[ij] = v;
+            se += (i == j ? 1.0 : 2.0) * v * d.H[ij];
+            if (i == j) st += v;
+        }
+        tileT[r][tx] = v;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        // element (J*32 + r, I*32 + tx) = tile(I,J)[tx][r]
+        const int i = J * 32 + r, j = I * 32 + tx;
+        if (i < n && j < n && (I != J ? true : j < i)) Pn[int64_t(i) * n + j] = tileT[tx][r];
+    }
+    se = block_sum(se, sh);
+    st = block_sum(st, sh);
+    if (threadIdx.x == 0) {
+        d.partials[int64_t(blockIdx.x) * kPartials + 0] = se;
+        d.partials[int64_t(blockIdx.x) * kPartials + 1] = st;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host driver.
+
+namespace {
+
+struct MatLayout {
+    double* X2;
+    double* X3;
+    double* Pw;       // workspace iterate (Pb[1])
+    uint8_t* planesP;
+    uint8_t* planesX;
+    int* expP;
+    int* expX;
+    uint64_t* maxP;
+    uint64_t* maxX;
+    double* rows;
+    int* rowbad;
+    double* e0;
+};
+
+int native_blocks(int n) { return int(std::min<int64_t>(2048, (int64_t(n) * n + 255) / 256)); }
+int native_pairs(int n) {
+    const int t = (n + 31) / 32;
+    return t * (t + 1) / 2;
+}
+int oz_tiles(int n) {
+    const int t = int(round_up(n, kTile) / kTile);
+    return t * (t + 1) / 2;
+}
+
+MatLayout carve_matrix(Carver& c, int n, int S, dmp_kind kind) {
+    MatLayout m{};
+    const size_t nn = size_t(n) * n;
+    m.X2 = c.take<double>(nn);
+    m.Pw = c.take<double>(nn);
+    if (kind == DMP_FP64_NATIVE) {
+        m.X3 = c.take<double>(nn);
+    } else {
+        m.planesP = c.take<uint8_t>(plane_bytes(n, n, S, kind));
+        m.planesX = c.take<uint8_t>(plane_bytes(n, n, S, kind));
+        m.expP = c.take<int>(round_up(n, kPad));
+        m.expX = c.take<int>(round_up(n, kPad));
+        m.maxP = c.take<uint64_t>(round_up(n, kPad));
+        m.maxX = c.take<uint64_t>(round_up(n, kPad));
+    }
+    m.rows = c.take<double>(3 * size_t(n));
+    m.rowbad = c.take<int>(n);
+    m.e0 = c.take<double>(kE0Blocks);
+    return m;
+}
+
+// Everything a group of matrices (same S and kind) needs on the device.
+struct GroupPlan {
+    int count = 0;
+    int S = 0;
+    dmp_kind kind = DMP_OZ_INT8;
+    std::vector<int> idx;             // positions in the caller's arrays
+    std::vector<MatLayout> lay;
+    PurDesc* pd = nullptr;            // [count]
+    DevState* st = nullptr;           // [count]
+    SplitDesc* splitP[2] = {nullptr, nullptr};  // [count] each
+    SplitDesc* splitX = nullptr;      // [count]
+    MatDesc* sq[2] = {nullptr, nullptr};
+    MatDesc* up[2] = {nullptr, nullptr};
+    Tile* tiles = nullptr;
+    double* partials = nullptr;
+    int ntiles = 0, units_rowmax = 0, units_digits = 0, max_n = 0;
+    int2* pairs = nullptr;            // native: tile pairs
+};
+
+size_t carve_group(Carver& c, GroupPlan& g, const int* n) {
+    size_t parts = 0;
+    g.lay.resize(g.count);
+    for (int b = 0; b < g.count; ++b) {
+        const int nb = n[g.idx[b]];
+        g.lay[b] = carve_matrix(c, nb, g.S, g.kind);
+        if (g.kind == DMP_FP64_NATIVE)
+            parts = std::max<size_t>(parts, std::max(native_blocks(nb), native_pairs(nb)));
+        else
+            parts += size_t(oz_tiles(nb));
+    }
+    g.pd = c.take<PurDesc>(g.count);
+    g.st = c.take<DevState>(g.count);
+    g.splitP[0] = c.take<SplitDesc>(g.count);
+    g.splitP[1] = c.take<SplitDesc>(g.count);
+    g.splitX = c.take<SplitDesc>(g.count);
+    g.sq[0] = c.take<MatDesc>(g.count);
+    g.sq[1] = c.take<MatDesc>(g.count);
+    g.up[0] = c.take<MatDesc>(g.count);
+    g.up[1] = c.take<MatDesc>(g.count);
+    g.tiles = c.take<Tile>(std::max<size_t>(1, g.kind == DMP_FP64_NATIVE ? 1 : parts));
+    g.partials = c.take<double>(std::max<size_t>(1, parts) * kPartials);
+    if (g.kind == DMP_FP64_NATIVE) {
+        int mx = 0;
+        for (int b = 0; b < g.count; ++b) mx = std::max(mx, native_pairs(n[g.idx[b]]));
+        g.pairs = c.take<int2>(std::max(1, mx));
+    }
+    return c.used();
+}
+
+// Fill the descriptor arrays (host side) and upload them.
+int upload_group(GroupPlan& g, const double* const* H, double* const* P, const int* n,
+                 const int* nocc, hipStream_t s, std::vector<std::vector<char>>& keep) {
+    const int cnt = g.count;
+    std::vector<PurDesc> pd(cnt);
+    std::vector<SplitDesc> sp0(cnt), sp1(cnt), sx(cnt);
+    std::vector<MatDesc> q0(cnt), q1(cnt), u0(cnt), u1(cnt);
+    std::vector<Tile> tiles;
+    int pbeg = 0, urow = 0, udig = 0;
+    g.max_n = 0;
+    for (int b = 0; b < cnt; ++b) {
+        const int m = g.idx[b], nb = n[m];
+        const MatLayout& L = g.lay[b];
+        g.max_n = std::max(g.max_n, nb);
+        PurDesc d{};
+        d.H = H[m];
+        d.Pb[0] = P[m];
+        d.Pb[1] = L.Pw;
+        d.X2 = L.X2;
+        d.X3 = L.X3;
+        d.rows = L.rows;
+        d.rowbad = L.rowbad;
+        d.e0 = L.e0;
+        d.partials = g.partials;
+        d.n = nb;
+        d.nocc = nocc[m];
+        if (g.kind == DMP_FP64_NATIVE) {
+            d.part_begin = 0;
+            d.part_end = 0;   // set per phase by the native driver
+        } else {
+            d.part_begin = pbeg;
+            pbeg += oz_tiles(nb);
+            d.part_end = pbeg;
+            append_tiles(tiles, int(round_up(nb, kTile) / kTile), int(round_up(nb, kTile) / kTile),
+                         true, uint32_t(b));
+        }
+        pd[b] = d;
+        if (g.kind == DMP_FP64_NATIVE) continue;
+        const int KC = int(chunks_of(nb, g.kind));
+        const int64_t rbs = int64_t(KC) * g.S * kFragBytes;
+        SplitDesc sd{};
+        sd.lda = nb;
+        sd.R = nb;
+        sd.K = nb;
+        sd.trans = 0;
+        sd.KC = KC;
+        sd.ub_rowmax = urow;
+        sd.ub_digits = udig;
+        sd.state_index = b;
+        urow += split_units_rowmax(nb);
+        udig += split_units_digits(nb, KC);
+        sd.A = P[m];
+        sd.maxbits = L.maxP;
+        sd.expo = L.expP;
+        sd.planes = L.planesP;
+        sp0[b] = sd;
+        sd.A = L.Pw;
+        sp1[b] = sd;
+        sd.A = L.X2;
+        sd.maxbits = L.maxX;
+        sd.expo = L.expX;
+        sd.planes = L.planesX;
+        sx[b] = sd;
+        MatDesc md{};
+        md.a_rb_stride = rbs;
+        md.b_rb_stride = rbs;
+        md.M = nb;
+        md.N = nb;
+        md.KC = KC;
+        md.ldc = nb;
+        md.state_index = b;
+        md.H = H[m];
+        md.X2 = L.X2;
+        // square: A = B = planes of P
+        md.pa = L.planesP;
+        md.pb = L.planesP;
+        md.ea = L.expP;
+        md.eb = L.expP;
+        md.out = L.X2;
+        md.P = P[m];
+        q0[b] = md;
+        md.P = L.Pw;
+        q1[b] = md;
+        // update: A = planes of X2, B = planes of P; P' into the other buffer
+        md.pa = L.planesX;
+        md.ea = L.expX;
+        md.P = P[m];
+        md.out = L.Pw;
+        u0[b] = md;
+        md.P = L.Pw;
+        md.out = P[m];
+        u1[b] = md;
+    }
+    g.ntiles = int(tiles.size());
+    g.units_rowmax = urow;
+    g.units_digits = udig;
+    auto up = [&](void* dst, const void* src, size_t bytes) -> int {
+        if (bytes == 0) return DMP_OK;
+        keep.emplace_back(static_cast<const char*>(src), static_cast<const char*>(src) + bytes);
+        DMP_CHECK_HIP(hipMemcpyAsync(dst, keep.back().data(), bytes, hipMemcpyHostToDevice, s));
+        return DMP_OK;
+    };
+    DMP_CHECK(up(g.pd, pd.data(), cnt * sizeof(PurDesc)));
+    if (g.kind != DMP_FP64_NATIVE) {
+        DMP_CHECK(up(g.splitP[0], sp0.data(), cnt * sizeof(SplitDesc)));
+        DMP_CHECK(up(g.splitP[1], sp1.data(), cnt * sizeof(SplitDesc)));
+        DMP_CHECK(up(g.splitX, sx.data(), cnt * sizeof(SplitDesc)));
+        DMP_CHECK(up(g.sq[0], q0.data(), cnt * sizeof(MatDesc)));
+        DMP_CHECK(up(g.sq[1], q1.data(), cnt * sizeof(MatDesc)));
+        DMP_CHECK(up(g.up[0], u0.data(), cnt * sizeof(MatDesc)));
+        DMP_CHECK(up(g.up[1], u1.data(), cnt * sizeof(MatDesc)));
+        DMP_CHECK(up(g.tiles, tiles.data(), tiles.size() * sizeof(Tile)));
+    }
+    return DMP_OK;
+}
+
+int launch_init(GroupPlan& g, double tol, int max_iter, hipStream_t s) {
+    k_gershgorin<<<dim3((g.max_n + 3) / 4, g.count), 256, 0, s>>>(g.pd);
+    k_finalize_init<<<g.count, 256, 0, s>>>(g.pd, g.st, tol, max_iter);
+    k_init_p0<<<dim3(kE0Blocks, g.count), 256, 0, s>>>(g.pd, g.st);
+    k_finalize_e0<<<g.count, 256, 0, s>>>(g.pd, g.st);
+    DMP_CHECK_HIP(hipGetLastError());
+    return DMP_OK;
+}
+
+double gemm_ops(const GroupPlan& g, const int* n) {
+    double t = 0.0;
+    for (int b = 0; b < g.count; ++b) {
+        const double m = n[g.idx[b]];
+        t += double(g.S) * (g.S + 1) * m * m * (m + 1) / 2.0;
+    }
+    return t;
+}
+
+int timed_gemm(GroupPlan& g, const GemmParams& p, int which, double ops, hipStream_t s,
+               std::vector<PendingTimer>* timers) {
+    PendingTimer t{};
+    if (timers) {
+        DMP_CHECK_HIP(hipEventCreate(&t.start));
+        DMP_CHECK_HIP(hipEventCreate(&t.stop));
+        DMP_CHECK_HIP(hipEventRecord(t.start, s));
+    }
+    DMP_CHECK(launch_ozgemm(g.S, g.kind, p, g.ntiles, s));
+    if (timers) {
+        DMP_CHECK_HIP(hipEventRecord(t.stop, s));
+        t.which = which;
+        t.ops = ops;
+        timers->push_back(t);
+    }
+    return DMP_OK;
+}
+
+// One Ozaki iteration of the whole group with iterate parity ``par``.
+int launch_oz_iteration(GroupPlan& g, int par, hipStream_t s,
+                        std::vector<PendingTimer>* timers = nullptr, double ops = 0.0) {
+    DMP_CHECK(launch_split_grouped_rowmax(g.splitP[par], g.count, g.units_rowmax, g.st, s));
+    DMP_CHECK(launch_split_grouped_digits(g.splitP[par], g.count, g.units_digits, g.S, g.kind, g.st, s));
+    GemmParams p{};
+    p.tiles = g.tiles;
+    p.descs = g.sq[par];
+    p.partials = g.partials;
+    p.states = g.st;
+    p.mode = EPI_SQUARE;
+    DMP_CHECK(timed_gemm(g, p, 0, ops, s, timers));
+    k_finalize_coef<<<g.count, 256, 0, s>>>(g.pd, g.st);
+    DMP_CHECK(launch_split_grouped_rowmax(g.splitX, g.count, g.units_rowmax, g.st, s));
+    DMP_CHECK(launch_split_grouped_digits(g.splitX, g.count, g.units_digits, g.S, g.kind, g.st, s));
+    p.descs = g.up[par];
+    p.mode = EPI_UPDATE;
+    DMP_CHECK(timed_gemm(g, p, 1, ops, s, timers));
+    k_finalize_iter<<<g.count, 256, 0, s>>>(g.pd, g.st);
+    DMP_CHECK_HIP(hipGetLastError());
+    return DMP_OK;
+}
+
+int iterations_per_sync(int max_n) {
+    if (max_n >= 4096) return 2;
+    if (max_n >= 1024) return 4;
+    return 8;
+}
+
+bool graphs_enabled() {
+    const char* e = std::getenv("DMP_NO_GRAPH");
+    return !(e && e[0] == '1');
+}
+
+// Run the Ozaki groups to completion; graph-captured batches of iterations.
+int run_oz_groups(std::vector<GroupPlan>& groups, int max_iter, hipStream_t s,
+                  std::vector<DevState>& host_st, const int* n) {
+    int max_n = 0;
+    for (auto& g : groups) max_n = std::max(max_n, g.max_n);
+    const int m = iterations_per_sync(max_n);
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    const bool timing = g_timing.on;
+    std::vector<PendingTimer> timers;
+    if (graphs_enabled() && !timing) {
+        hipStream_t cap = nullptr;
+        if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) == hipSuccess) {
+            bool ok = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            for (int it = 0; ok && it < m; ++it)
+                for (auto& g : groups) ok = ok && launch_oz_iteration(g, it & 1, cap) == DMP_OK;
+            hipGraph_t gr = nullptr;
+            const bool ended = hipStreamEndCapture(cap, &gr) == hipSuccess;
+            if (ok && ended && gr && hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0) == hipSuccess) {
+                graph = gr;
+            } else {
+                if (gr) (void)hipGraphDestroy(gr);
+                exec = nullptr;
+            }
+            (void)hipStreamDestroy(cap);
+            (void)hipGetLastError();
+            clear_error();
+        }
+    }
+    int status = DMP_OK;
+    const int rounds = (max_iter + m - 1) / m + 1;
+    for (int r = 0; r < rounds; ++r) {
+        if (exec) {
+            if (hipGraphLaunch(exec, s) != hipSuccess) {
+                set_error("hipGraphLaunch failed");
+                status = DMP_EHIP;
+                break;
+            }
+        } else {
+            for (int it = 0; it < m && status == DMP_OK; ++it)
+                for (auto& g : groups)
+                    status = launch_oz_iteration(g, it & 1, s, timing ? &timers : nullptr,
+                                                 gemm_ops(g, n));
+            if (status != DMP_OK) break;
+        }
+        bool all = true;
+        size_t off = 0;
+        for (auto& g : groups) {
+            if (hipMemcpyAsync(host_st.data() + off, g.st, g.count * sizeof(DevState),
+                               hipMemcpyDeviceToHost, s) != hipSuccess) {
+                set_error("state readback failed");
+                status = DMP_EHIP;
+            }
+            off += g.count;
+        }
+        if (status != DMP_OK) break;
+        if (hipStreamSynchronize(s) != hipSuccess) {
+            set_error("hipStreamSynchronize failed: %s", hipGetErrorString(hipGetLastError()));
+            status = DMP_EHIP;
+            break;
+        }
+        // launches of finished matrices exit at once: count only the
+        // iterations that ran (iters advanced), one square + one update each
+        for (auto& t : timers) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, t.start, t.stop) == hipSuccess) {
+                g_timing.ms[t.which] += ms;
+                g_timing.launches[t.which] += 1;
+                g_timing.ops[t.which] += t.ops;
+            }
+            (void)hipEventDestroy(t.start);
+            (void)hipEventDestroy(t.stop);
+        }
+        timers.clear();
+        for (auto& h : host_st) all = all && h.done;
+        if (all) break;
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    return status;
+}
+
+// Native FP64 purification of one matrix (group of one), host-checked
+// every iteration.
+int run_native(GroupPlan& g, int max_iter, hipStream_t s, DevState& host) {
+    const int n = g.max_n;
+    const MatLayout& L = g.lay[0];
+    PurDesc hd{};
+    DMP_CHECK_HIP(hipMemcpyAsync(&hd, g.pd, sizeof(PurDesc), hipMemcpyDeviceToHost, s));
+    DMP_CHECK_HIP(hipStreamSynchronize(s));
+    const int nb = native_blocks(n), np = native_pairs(n);
+    std::vector<int2> pairs;
+    const int t = (n + 31) / 32;
+    for (int i = 0; i < t; ++i)
+        for (int j = i; j < t; ++j) pairs.push_back(int2{i, j});
+    DMP_CHECK_HIP(hipMemcpyAsync(g.pairs, pairs.data(), pairs.size() * sizeof(int2),
+                                 hipMemcpyHostToDevice, s));
+    for (int it = 0; it < max_iter; ++it) {
+        DMP_CHECK_HIP(hipMemcpyAsync(&host, g.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+        DMP_CHECK_HIP(hipStreamSynchronize(s));
+        if (host.done) break;
+        const double* P = host.iters & 1 ? L.Pw : hd.Pb[0];
+        DMP_CHECK(native_dgemm(s, false, false, n, n, n, P, n, P, n, L.X2, n));
+        // two host copies: each stays unmodified until the next iteration's sync
+        PurDesc dsq = hd, dup = hd;
+        dsq.part_begin = 0;
+        dsq.part_end = nb;
+        dup.part_begin = 0;
+        dup.part_end = np;
+        DMP_CHECK_HIP(hipMemcpyAsync(g.pd, &dsq, sizeof(PurDesc), hipMemcpyHostToDevice, s));
+        k_native_square<<<nb, 256, 0, s>>>(g.pd, g.st, nb);
+        k_finalize_coef<<<1, 256, 0, s>>>(g.pd, g.st);
+        DMP_CHECK(native_dgemm(s, false, false, n, n, n, L.X2, n, P, n, L.X3, n));
+        DMP_CHECK_HIP(hipMemcpyAsync(g.pd, &dup, sizeof(PurDesc), hipMemcpyHostToDevice, s));
+        k_native_update<<<np, 256, 0, s>>>(g.pd, g.st, g.pairs);
+        k_finalize_iter<<<1, 256, 0, s>>>(g.pd, g.st);
+        DMP_CHECK_HIP(hipGetLastError());
+    }
+    DMP_CHECK_HIP(hipMemcpyAsync(&host, g.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    DMP_CHECK_HIP(hipStreamSynchronize(s));
+    return DMP_OK;
+}
+
+void fill_info(const DevState& h, int S, dmp_kind kind, dmp_info* info) {
+    if (!info) return;
+    info->iters = h.iters;
+    info->stop_reason = h.stop_reason;
+    info->slices = kind == DMP_FP64_NATIVE ? 0 : S;
+    info->kind = int(kind);
+    info->E = h.E;
+    info->last_dE = h.dE;
+    info->trace = h.trace_p;
+    info->idem = h.t1;
+    info->h_min = h.h_min;
+    info->h_max = h.h_max;
+    info->mu = h.mu;
+    info->lambda = h.lambda;
+}
+
+}  // namespace
+
+int validate_purify_args(const double* H, int n, int nocc, double tol, int max_iter, const double* P) {
+    if (n < 1 || nocc < 0 || nocc > n) {
+        set_error("need n >= 1 and 0 <= nocc <= n (n=%d, nocc=%d)", n, nocc);
+        return DMP_EINVAL;
+    }
+    if (!(tol > 0.0) || max_iter < 1) {
+        set_error("need tol > 0 and max_iter >= 1");
+        return DMP_EINVAL;
+    }
+    if (!H || !P || H == P) {
+        set_error("H and P must be distinct non-null device pointers");
+        return DMP_EINVAL;
+    }
+    if (n > 65535 * kTile) {
+        set_error("n too large");
+        return DMP_EINVAL;
+    }
+    return DMP_OK;
+}
+
+// Purify count matrices that share S and kind; used by both entry points.
+int purify_many(int count, const double* const* H, const int* n, const int* nocc, double tol,
+                const int* slices, dmp_kind kind, int max_iter, double* const* P, double* E,
+                dmp_info* info, void* ws, size_t ws_bytes, hipStream_t s, size_t* need_out) {
+    // partition by slice count
+    std::vector<GroupPlan> groups;
+    for (int b = 0; b < count; ++b) {
+        const int S = kind == DMP_FP64_NATIVE ? 0 : slices[b];
+        GroupPlan* g = nullptr;
+        for (auto& x : groups)
+            if (x.S == S && kind != DMP_FP64_NATIVE) g = &x;
+        if (!g) {
+            groups.emplace_back();
+            g = &groups.back();
+            g->S = S;
+            g->kind = kind;
+        }
+        g->idx.push_back(b);
+        g->count++;
+    }
+    Carver c(ws);
+    for (auto& g : groups) carve_group(c, g, n);
+    if (need_out) *need_out = c.used();
+    if (ws == nullptr) return DMP_OK;
+    if (ws_bytes < c.used()) {
+        set_error("workspace of %zu bytes required", c.used());
+        return DMP_ENOMEM;
+    }
+    std::vector<std::vector<char>> keep;
+    for (auto& g : groups) {
+        DMP_CHECK(upload_group(g, H, P, n, nocc, s, keep));
+        DMP_CHECK(launch_init(g, tol, max_iter, s));
+    }
+    std::vector<DevState> host_st(count);
+    {
+        size_t off = 0;
+        for (auto& g : groups) {
+            DMP_CHECK_HIP(hipMemcpyAsync(host_st.data() + off, g.st, g.count * sizeof(DevState),
+                                         hipMemcpyDeviceToHost, s));
+            off += g.count;
+        }
+        DMP_CHECK_HIP(hipStreamSynchronize(s));
+        keep.clear();
+        for (auto& h : host_st)
+            if (h.nonfinite) {
+                set_error("H holds a non-finite entry");
+                return DMP_ENONFINITE;
+            }
+    }
+    if (kind == DMP_FP64_NATIVE) {
+        size_t off = 0;
+        for (auto& g : groups) {
+            DMP_CHECK(run_native(g, max_iter, s, host_st[off]));
+            off += g.count;
+        }
+    } else {
+        DMP_CHECK(run_oz_groups(groups, max_iter, s, host_st, n));
+    }
+    // results: final iterate lives in Pb[iters & 1]
+    int status = DMP_OK;
+    size_t off = 0;
+    for (auto& g : groups) {
+        for (int b = 0; b < g.count; ++b) {
+            const DevState& h = host_st[off + b];
+            const int m = g.idx[b];
+            if (h.iters & 1)
+                DMP_CHECK_HIP(hipMemcpyAsync(P[m], g.lay[b].Pw, size_t(n[m]) * n[m] * sizeof(double),
+                                             hipMemcpyDeviceToDevice, s));
+            if (E) E[m] = h.E;
+            fill_info(h, g.S, kind, info ? info + m : nullptr);
+            if (h.stop_reason != DMP_STOP_CONVERGED) status = DMP_NOT_CONVERGED;
+        }
+        off += g.count;
+    }
+    DMP_CHECK_HIP(hipStreamSynchronize(s));
+    return status;
+}
+
+}  // namespace dmp
+
+using namespace dmp;
+
+extern "C" {
+
+void dmp_timing_enable(int on) { g_timing.on = on != 0; }
+
+void dmp_timing_reset(void) {
+    const bool on = g_timing.on;
+    g_timing = TimingState{};
+    g_timing.on = on;
+}
+
+int dmp_timing_read(int which, double* total_ms, long long* launches, double* ops) {
+    if (which < 0 || which > 1) return DMP_EINVAL;
+    if (total_ms) *total_ms = g_timing.ms[which];
+    if (launches) *launches = g_timing.launches[which];
+    if (ops) *ops = g_timing.ops[which];
+    return DMP_OK;
+}
+
+size_t dmp_purify_workspace_bytes(int n, int slices, dmp_kind kind) {
+    if (n < 1) return 0;
+    if (kind != DMP_FP64_NATIVE && (slices < 1 || slices > kMaxSlices)) return 0;
+    size_t need = 0;
+    const double* h = nullptr;
+    double* p = nullptr;
+    int nocc = 0;
+    purify_many(1, &h, &n, &nocc, 1.0, &slices, kind, 1, &p, nullptr, nullptr, nullptr, 0,
+                nullptr, &need);
+    return need;
+}
+
+int dmp_purify(const double* H, int n, int nocc, double tol, int slices, dmp_kind kind,
+               int max_iter, double* P, double* E, dmp_info* info, void* ws, size_t ws_bytes,
+               void* stream) {
+    clear_error();
+    DMP_CHECK(check_kind_slices(kind, slices));
+    DMP_CHECK(validate_purify_args(H, n, nocc, tol, max_iter, P));
+    if (kind != DMP_FP64_NATIVE && n > max_k_for_slices(slices)) {
+        set_error("n = %d exceeds the exact INT32 range for %d slices", n, slices);
+        return DMP_EINVAL;
+    }
+    if (ws == nullptr) {
+        set_error("workspace of %zu bytes required", dmp_purify_workspace_bytes(n, slices, kind));
+        return DMP_ENOMEM;
+    }
+    return purify_many(1, &H, &n, &nocc, tol, &slices, kind, max_iter, &P, E, info, ws, ws_bytes,
+                       static_cast<hipStream_t>(stream), nullptr);
+}
+
+}  // extern "C"

@@ -1,0 +1,146 @@
+"""GPU parity of the purification against the CPU oracle (C ABI)."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import canonical, projector
+from paper_2407_13299_amd.workloads import (spectrum_hamiltonian,
+                                            tight_binding_hamiltonian, workload)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+dmp = pytest.importorskip("paper_2407_13299_amd")
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TOL_P = 1e-10      # max |dP| against the eigendecomposition projector
+TOL_E = 1e-8       # |dE| in Ha
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def gpu_purify(h, nocc, **kw):
+    p, e, info = dmp.purify(dev(h), nocc, **kw)
+    torch.cuda.synchronize()
+    return p.cpu().numpy(), e, info
+
+
+@pytest.mark.parametrize("kind,s", [("native", 0), ("int8", 7), ("fp16", 7), ("int8", 8)])
+def test_small_spectrum(kind, s):
+    w = workload("small_spectrum")
+    h, nocc = w["H"], w["nocc"]
+    p, e, info = gpu_purify(h, nocc, tol=w["tol"], slices=max(s, 1), kind=kind)
+    p_ref, e_ref, _, _ = projector.eigh_projector(h, nocc)
+    assert info["stop"] == "converged"
+    assert np.max(np.abs(p - p_ref)) < TOL_P
+    assert abs(e - e_ref) < TOL_E
+    assert np.array_equal(p, p.T)
+    ref = canonical.purify(h, nocc, tol=w["tol"])
+    assert abs(info["iters"] - ref["iters"]) <= 1
+    assert abs(info["trace"] - nocc) < 1e-9
+
+
+@pytest.mark.parametrize("kind", ["int8", "fp16"])
+def test_tight_binding_2048(kind):
+    w = workload("tb_2048")
+    h, nocc = w["H"], w["nocc"]
+    p, e, info = gpu_purify(h, nocc, tol=w["tol"], slices=7, kind=kind)
+    p_ref, e_ref, _, gap = projector.eigh_projector(h, nocc)
+    m = projector.measures(p, e, h, nocc, p_ref, e_ref)
+    assert info["stop"] == "converged", info
+    assert m["max_dP"] < TOL_P, m
+    assert m["dE"] < TOL_E, m
+    assert m["trace_err"] < 1e-8
+    sim = canonical.eigen_simulate(h, nocc, tol=w["tol"])
+    assert abs(info["iters"] - sim["iters"]) <= 1
+
+
+def test_native_matches_ozaki_iterations_2048():
+    w = workload("tb_2048")
+    h, nocc = w["H"], w["nocc"]
+    _, _, i64 = gpu_purify(h, nocc, tol=w["tol"], kind="native")
+    _, _, i8 = gpu_purify(h, nocc, tol=w["tol"], slices=7, kind="int8")
+    assert i64["iters"] == i8["iters"]
+
+
+def test_slice_sweep_error_decreases():
+    """Error against slice count on the n = 2048 tight-binding workload."""
+    w = workload("tb_2048")
+    h, nocc = w["H"], w["nocc"]
+    p_ref, e_ref, _, _ = projector.eigh_projector(h, nocc)
+    errs = {}
+    for kind in ("int8", "fp16"):
+        for s in range(2, 9):
+            p, e, info = gpu_purify(h, nocc, tol=w["tol"], slices=s, kind=kind)
+            errs[(kind, s)] = (float(np.max(np.abs(p - p_ref))), abs(e - e_ref), info["stop"])
+        for s in range(4, 8):
+            assert errs[(kind, s + 1)][0] < errs[(kind, s)][0]
+        assert errs[(kind, 7)][0] < TOL_P and errs[(kind, 8)][0] < TOL_P
+    print("slice sweep", errs)
+
+
+@pytest.mark.parametrize("n", [2, 3, 63, 65, 130, 200])
+def test_ragged_sizes(n):
+    nocc = n // 2
+    h, _, _ = spectrum_hamiltonian(n, nocc, seed=n)
+    p, e, info = gpu_purify(h, nocc, tol=1e-12, slices=8, kind="int8")
+    p_ref, e_ref, _, _ = projector.eigh_projector(h, nocc)
+    assert np.max(np.abs(p - p_ref)) < TOL_P
+    assert abs(e - e_ref) < TOL_E
+
+
+def test_special_occupations_and_errors():
+    h, _, _ = spectrum_hamiltonian(70, 35, seed=1)
+    p, e, info = gpu_purify(h, 0, slices=7)
+    assert np.array_equal(p, np.zeros_like(h)) and e == 0.0 and info["iters"] == 0
+    p, e, info = gpu_purify(h, 70, slices=7)
+    assert np.array_equal(p, np.eye(70)) and abs(e - np.trace(h)) < 1e-12
+    bad = h.copy()
+    bad[3, 5] = np.nan
+    with pytest.raises(dmp._lib.DmpError, match="ENONFINITE"):
+        gpu_purify(bad, 35, slices=7)
+    p1, e1, i1 = gpu_purify(h, 1, slices=7)
+    p_ref, e_ref, _, _ = projector.eigh_projector(h, 1)
+    assert np.max(np.abs(p1 - p_ref)) < TOL_P
+
+
+def test_low_slices_stop_without_convergence():
+    h = tight_binding_hamiltonian(4, 4, 4, seed=1)
+    p, e, info = gpu_purify(h, 64, tol=1e-8, slices=2, kind="int8", max_iter=100)
+    assert info["stop"] in ("stagnated", "max_iter", "nonfinite")
+    p, e, info = gpu_purify(h, 64, tol=1e-8, slices=7, kind="int8", max_iter=5)
+    assert info["stop"] == "max_iter" and info["iters"] == 5
+
+
+def test_bitwise_deterministic():
+    w = workload("small_spectrum")
+    a = gpu_purify(w["H"], w["nocc"], tol=1e-12, slices=7)
+    b = gpu_purify(w["H"], w["nocc"], tol=1e-12, slices=7)
+    assert np.array_equal(a[0], b[0]) and a[1] == b[1]
+
+
+def test_full_size_tb_8192():
+    """n = 8192 at the benchmark configuration: stored oracle samples."""
+    ref = np.load(os.path.join(GOLDEN, "tb8192_reference.npz"))
+    w = workload("tb_8192")
+    h, nocc = w["H"], w["nocc"]
+    chk = np.array([h.sum(), np.abs(h).sum(), h[0, 0], h[-1, -1]])
+    assert np.allclose(chk, ref["H_checksum"], rtol=0, atol=1e-9)
+    hd = dev(h)
+    del h
+    p, e, info = dmp.purify(hd, nocc, tol=w["tol"], slices=7, kind="int8")
+    torch.cuda.synchronize()
+    assert info["stop"] == "converged", info
+    assert abs(e - float(ref["E"])) < TOL_E
+    rows = p[torch.from_numpy(ref["rows"]).cuda()].cpu().numpy()
+    assert np.max(np.abs(rows - ref["P_rows"])) < TOL_P
+    samp = p[torch.from_numpy(ref["si"]).cuda(), torch.from_numpy(ref["sj"]).cuda()].cpu().numpy()
+    assert np.max(np.abs(samp - ref["P_samples"])) < TOL_P
+    assert abs(float(torch.trace(p)) - nocc) < 1e-8
+    idem = torch.max(torch.abs(p @ p - p)).item()
+    assert idem < 1e-10
+    comm = torch.linalg.norm(hd @ p - p @ hd).item()
+    assert comm < 1e-8
+    assert torch.equal(p, p.T)
