@@ -41,8 +41,11 @@ void clear_error();
 //   FP16: CK = 16 (one v_mfma_f32_32x32x16_f16 per slice pair and chunk)
 constexpr int kFragRows = 32;
 constexpr int kFragBytes = 1024;
-constexpr int kTile = 64;            // GEMM output tile (2 x 2 fragments)
-constexpr int kPad = 64;             // row / reduction padding of the planes
+constexpr int kTileM = 128;          // GEMM output tile rows (4 fragment rows)
+constexpr int kTileN = 64;           // GEMM output tile columns (2 fragment rows)
+constexpr int kGemmThreads = 512;    // 8 wavefronts, one 32 x 32 quadrant each
+constexpr int kPad = 128;            // row padding of the digit planes
+constexpr int kKPad = 64;            // reduction padding of the digit planes
 constexpr int kMaxSlices = 12;
 constexpr int kTopBits = 6;          // fractional bits of the first digit
 constexpr int kDigitBits = 8;        // bits of every further digit
@@ -59,12 +62,12 @@ inline int64_t max_k_for_slices(int s) { return ((1ll << 31) - 1) / (int64_t(s) 
 
 // Bytes of the digit planes of an R x K operand.
 inline size_t plane_bytes(int64_t r, int64_t k, int s, dmp_kind kind) {
-    return size_t(round_up(r, kPad)) * size_t(round_up(k, kPad)) * size_t(s) *
+    return size_t(round_up(r, kPad)) * size_t(round_up(k, kKPad)) * size_t(s) *
            (kind == DMP_OZ_FP16 ? 2 : 1);
 }
 
-// One output tile of a (possibly grouped) GEMM: 64 x 64 block (I, J) of
-// matrix ``mat`` of a batch.
+// One output tile of a (possibly grouped) GEMM: rows [128 I, 128 I + 128),
+// columns [64 J, 64 J + 64) of matrix ``mat`` of a batch.
 struct Tile {
     uint16_t I, J;
     uint32_t mat;

@@ -89,7 +89,7 @@ int dmp_ozaki_gemm(char transA, char transB, int m, int n, int k, const double* 
                   (long long)max_k_for_slices(slices));
         return DMP_EINVAL;
     }
-    if (m > 65535 * kTile || n > 65535 * kTile) {
+    if (m > 65535 * kTileN || n > 65535 * kTileN) {
         set_error("matrix too large");
         return DMP_EINVAL;
     }
@@ -125,7 +125,7 @@ int dmp_ozaki_gemm(char transA, char transB, int m, int n, int k, const double* 
     DMP_CHECK(launch_split(da, slices, kind, nullptr, s));
     DMP_CHECK(launch_split(db, slices, kind, nullptr, s));
 
-    const int tm = int(round_up(m, kTile) / kTile), tn = int(round_up(n, kTile) / kTile);
+    const int tm = tile_rows(m), tn = tile_cols(n);
     const Tile* tiles = nullptr;
     DMP_CHECK(cached_tiles(tm, tn, false, &tiles));
     GemmParams p{};
@@ -157,7 +157,7 @@ size_t dmp_gemm_batched_workspace_bytes(int count, const int* m, const int* n, c
     size_t tiles = 0;
     for (int b = 0; b < count; ++b) {
         if (kind != DMP_FP64_NATIVE) carve_gemm(c, m[b], n[b], k[b], slices, kind);
-        tiles += size_t(round_up(m[b], kTile) / kTile) * size_t(round_up(n[b], kTile) / kTile);
+        tiles += size_t(tile_rows(m[b])) * size_t(tile_cols(n[b]));
     }
     c.take<SplitDesc>(2 * size_t(count));
     c.take<MatDesc>(count);
@@ -252,8 +252,7 @@ int dmp_ozaki_gemm_batched(int count, const int* m, const int* n, const int* k,
         q.ldc = n[b];
         q.state_index = -1;
         md[b] = q;
-        append_tiles(tiles, int(round_up(m[b], kTile) / kTile), int(round_up(n[b], kTile) / kTile),
-                     false, uint32_t(b));
+        append_tiles(tiles, tile_rows(m[b]), tile_cols(n[b]), false, uint32_t(b));
     }
     Tile* t_dev = c.take<Tile>(tiles.size());
     DMP_CHECK_HIP(hipMemcpyAsync(sd_dev, sa.data(), count * sizeof(SplitDesc), hipMemcpyHostToDevice, s));

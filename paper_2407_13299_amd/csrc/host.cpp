@@ -20,16 +20,30 @@ void set_error(const char* fmt, ...) {
 
 void clear_error() { g_error[0] = '\0'; }
 
+bool tile_in_upper(int i, int j) { return kTileN * j + kTileN - 1 >= kTileM * i; }
+
 void append_tiles(std::vector<Tile>& out, int tm, int tn, bool upper, uint32_t mat) {
-    constexpr int G = 8;
-    const int sm = (tm + G - 1) / G, sn = (tn + G - 1) / G;
+    // super-tiles of GI x GJ tiles = 512 x 512 elements
+    constexpr int GI = 512 / kTileM, GJ = 512 / kTileN;
+    const int sm = (tm + GI - 1) / GI, sn = (tn + GJ - 1) / GJ;
     for (int si = 0; si < sm; ++si)
-        for (int sj = upper ? si : 0; sj < sn; ++sj)
-            for (int i = si * G; i < std::min(tm, si * G + G); ++i)
-                for (int j = sj * G; j < std::min(tn, sj * G + G); ++j) {
-                    if (upper && j < i) continue;
+        for (int sj = 0; sj < sn; ++sj)
+            for (int i = si * GI; i < std::min(tm, si * GI + GI); ++i)
+                for (int j = sj * GJ; j < std::min(tn, sj * GJ + GJ); ++j) {
+                    if (upper && !tile_in_upper(i, j)) continue;
                     out.push_back(Tile{uint16_t(i), uint16_t(j), mat});
                 }
+}
+
+int tile_rows(int m) { return int(round_up(m, kTileM) / kTileM); }
+int tile_cols(int n) { return int(round_up(n, kTileN) / kTileN); }
+
+int upper_tile_count(int n) {
+    const int tm = tile_rows(n), tn = tile_cols(n);
+    int c = 0;
+    for (int i = 0; i < tm; ++i)
+        for (int j = 0; j < tn; ++j) c += tile_in_upper(i, j) ? 1 : 0;
+    return c;
 }
 
 int cached_tiles(int tm, int tn, bool upper, const Tile** out) {
@@ -110,7 +124,7 @@ int check_kind_slices(dmp_kind kind, int slices) {
     return DMP_OK;
 }
 
-int64_t chunks_of(int k, dmp_kind kind) { return round_up(k, kPad) / chunk_k(kind); }
+int64_t chunks_of(int k, dmp_kind kind) { return round_up(k, kKPad) / chunk_k(kind); }
 
 }  // namespace dmp
 

@@ -30,9 +30,13 @@ private:
     size_t off_ = 0;
 };
 
-// Order of the 64 x 64 output tiles of one matrix: 8 x 8 super-tiles,
-// row-major over super-tiles and within each; ``upper`` keeps I <= J only.
+// Order of the 128 x 64 output tiles of one matrix: 512 x 512 super-tiles,
+// row-major over super-tiles and within each; ``upper`` keeps the tiles that
+// reach the upper triangle (column >= row somewhere in the tile).
 void append_tiles(std::vector<Tile>& out, int tm, int tn, bool upper, uint32_t mat);
+int tile_rows(int m);
+int tile_cols(int n);
+int upper_tile_count(int n);
 
 // Device copy of the tile order of a single tm x tn product, cached per
 // device for the life of the process.

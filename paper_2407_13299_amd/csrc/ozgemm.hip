@@ -1,30 +1,35 @@
 // Slice-pair products of the Ozaki scheme (Sec. 2.4) on gfx950 matrix cores,
 // with the FP64 summation and the purification work fused into the epilogue.
 //
-// A workgroup owns one 64 x 64 output tile; its four wavefronts own 32 x 32
-// quadrants.  For every chunk of the reduction (32 INT8 or 16 FP16 elements)
-// the S digit planes of the tile's two 32-row blocks of each operand (4 S KiB,
-// contiguous runs in HBM) are staged once through double-buffered LDS and
-// every wavefront forms all S (S + 1) / 2 slice pairs (i + j <= S + 1) from
-// registers:
+// A workgroup of 8 wavefronts owns one 128 x 64 output tile (4 x 2 quadrants
+// of 32 x 32, one per wavefront).  The reduction runs in chunks (32 INT8 or
+// 16 FP16 elements); one chunk of the tile is 6 S fragment blocks of 1 KiB
+// (4 row blocks of the left operand, 2 of the right, S digit planes each),
+// contiguous in HBM per row block.  Loads run two chunks ahead of the MFMA
+// work through two register sets into two LDS buffers, with one barrier per
+// chunk (each step: load chunk c + 2 into the free register set, MFMAs on
+// chunk c from LDS, store chunk c + 1 into the other LDS buffer, barrier).
+// Every wavefront forms all S (S + 1) / 2 slice pairs (i + j <= S + 1):
 //   INT8: v_mfma_i32_32x32x32_i8, exact INT32 sums; one accumulator per
 //         anti-diagonal group g = i + j (products of the same weight
 //         2^-(8g - 4) add exactly), (g - 1) k 2^14 < 2^31 checked on the host;
-//   FP16: v_mfma_f32_32x32x16_f16; the FP32 sum of one chunk is an integer
-//         below 2^24 (16 (g - 1) 2^14 <= 2^24 for g - 1 <= 64), so it is exact,
-//         and it is converted to INT32 and added to the group accumulator.
+//         loop over the left slice i (inner: right slice j), so consecutive
+//         MFMAs feed different accumulators;
+//   FP16: v_mfma_f32_32x32x16_f16; per group and chunk the FP32 sum is an
+//         integer of magnitude <= 16 (g - 1) 2^14 <= 2^24, hence exact, and is
+//         converted to INT32 and added to the group accumulator.
 // Epilogue, per element: Horner over the groups from the smallest weight up,
 //   h = G_{S+1};  h = h 2^-8 + G_g  (g = S .. 2);  C = h 2^(e_i + f_j - 12),
-// which equals adding the scaled group sums smallest first (the scaling by
-// powers of two is exact).  Then, by mode:
+// equal to adding the scaled group sums smallest first (power-of-two
+// scalings are exact).  Then, by mode:
 //   EPI_STORE   C (rows < M, columns < N)
-//   EPI_SQUARE  X2 = P P on tiles I <= J, mirrored; tile partials of
+//   EPI_SQUARE  X2 = P P for row <= col, mirrored; tile partials of
 //               tr(P - X2) and sum_ij X2_ij (delta_ij - P_ij) = tr(X2 - P^3)
-//   EPI_UPDATE  P' = alpha P + beta X2 + gamma (X2 P) on tiles I <= J,
+//   EPI_UPDATE  P' = alpha P + beta X2 + gamma (X2 P) for row <= col,
 //               mirrored; tile partials of tr(P' H) and tr P'
-// In the two purification modes a diagonal tile keeps only its upper
-// triangle and mirrors it, so every iterate is exactly symmetric and its row
-// digits also serve as its column digits.
+// In the purification modes only the upper triangle is computed and kept,
+// so every iterate is exactly symmetric and its row digits also serve as its
+// column digits.
 #include "common.hpp"
 
 namespace dmp {
@@ -34,57 +39,76 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 
+// Workgroup barrier without the memory fence __syncthreads() implies (that
+// fence would also wait for the prefetch loads in flight); the signal fences
+// keep the compiler from moving memory accesses across it, and LDS
+// visibility is ordered by the explicit lgkmcnt(0) before each barrier.
+__device__ inline void bare_barrier() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// s_waitcnt lgkmcnt(0) (gfx9 encoding: vmcnt and expcnt fields at their
+// maximum, i.e. not waited on)
+__device__ inline void wait_lgkm0() {
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 __device__ inline double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
 }
 
-// Two workgroups per CU while the group accumulators, operand fragments and
-// staging registers fit in 256 registers per lane; one beyond that.
 template <int S, bool FP16>
-struct MinBlocks { static constexpr int value = (FP16 ? S <= 5 : S <= 8) ? 2 : 1; };
+__global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
+    constexpr int BLOCKS = 6 * S;                 // 1 KiB blocks per chunk
+    constexpr int STAGE = BLOCKS * kFragBytes;
+    constexpr int WAVES = kGemmThreads / 64;
+    constexpr int PER = (BLOCKS + WAVES - 1) / WAVES;  // loads per thread per chunk
+    __shared__ __align__(16) uint8_t lds[2][STAGE];
+    __shared__ double red[WAVES][kPartials];
 
-template <int S, bool FP16>
-__global__ __launch_bounds__(256, (MinBlocks<S, FP16>::value)) void k_ozgemm(GemmParams p) {
-    constexpr int PLANE_RUN = S * kFragBytes;          // bytes of one (rb, chunk)
-    constexpr int U4_PER_THREAD = S;                   // 4 runs / 256 threads
-    __shared__ __align__(16) uint8_t lds[2][4][PLANE_RUN];
-    __shared__ double red[4][kPartials];
-
-    // XCD-aware block order: hardware hands consecutive blocks to the 8 XCDs
-    // in turn; give every XCD one contiguous slice of the tile list.
+    // XCD-aware block order: the hardware hands consecutive blocks to the 8
+    // XCDs in turn; give every XCD one contiguous slice of the tile list.
     const int nb = gridDim.x, b = blockIdx.x;
     const int xcd = b & 7, q = nb >> 3, rem = nb & 7, loc = b >> 3;
     const int t = (xcd < rem) ? xcd * (q + 1) + loc : rem * (q + 1) + (xcd - rem) * q + loc;
     const Tile tile = p.tiles[t];
-    const MatDesc& d = p.descs ? p.descs[tile.mat] : p.one;
+    const MatDesc d = p.descs ? p.descs[tile.mat] : p.one;
     const DevState* st = p.states ? p.states + d.state_index : nullptr;
     if (st != nullptr && st->done) return;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int I = tile.I, J = tile.J;
-    const uint8_t* a0 = d.pa + int64_t(2 * I) * d.a_rb_stride;
-    const uint8_t* b0 = d.pb + int64_t(2 * J) * d.b_rb_stride;
     const int KC = d.KC;
+    const int64_t a_rb = d.a_rb_stride, b_rb = d.b_rb_stride;
+    // left operand row blocks 4I..4I+3, right operand row blocks 2J, 2J+1
+    const uint8_t* a0 = d.pa + int64_t(4 * I) * a_rb + lane * 16;
+    const uint8_t* b0 = d.pb + int64_t(2 * J) * b_rb + lane * 16;
 
-    uint4 stage[U4_PER_THREAD];
-    auto gload = [&](int kc) {
+    // piece i of this thread: block i * WAVES + wave (wave-uniform), lane.
+    // Every wavefront issues PER loads per chunk (a block index past the end
+    // re-reads block 0 and is not stored), so the count of loads in flight is
+    // the same on every path and the compiler's waits stay exact.
+    auto gload = [&](int kc, v4i (&r)[PER]) __attribute__((always_inline)) {
 #pragma unroll
-        for (int r = 0; r < U4_PER_THREAD; ++r) {
-            const int qi = r * 256 + tid;                  // uint4 index in 4 runs
-            const int ob = qi / (S * 64), w = qi % (S * 64);
-            const uint8_t* base = ob < 2 ? a0 + int64_t(ob) * d.a_rb_stride
-                                         : b0 + int64_t(ob - 2) * d.b_rb_stride;
-            stage[r] = *reinterpret_cast<const uint4*>(base + int64_t(kc) * PLANE_RUN + w * 16);
+        for (int i = 0; i < PER; ++i) {
+            const int blk0 = i * WAVES + wave;
+            const int blk = blk0 < BLOCKS ? blk0 : 0;
+            const int ob = blk / S, s = blk % S;
+            const uint8_t* src = ob < 4 ? a0 + int64_t(ob) * a_rb : b0 + int64_t(ob - 4) * b_rb;
+            r[i] = *reinterpret_cast<const v4i*>(src + (int64_t(kc) * S + s) * kFragBytes);
         }
     };
-    auto lstore = [&](int buf) {
+    auto lstore = [&](int buf, const v4i (&r)[PER]) __attribute__((always_inline)) {
 #pragma unroll
-        for (int r = 0; r < U4_PER_THREAD; ++r) {
-            const int qi = r * 256 + tid;
-            const int ob = qi / (S * 64), w = qi % (S * 64);
-            *reinterpret_cast<uint4*>(&lds[buf][ob][w * 16]) = stage[r];
+        for (int i = 0; i < PER; ++i) {
+            const int blk = i * WAVES + wave;
+            if (blk < BLOCKS)
+                *reinterpret_cast<v4i*>(&lds[buf][blk * kFragBytes + lane * 16]) = r[i];
         }
     };
 
@@ -94,31 +118,29 @@ __global__ __launch_bounds__(256, (MinBlocks<S, FP16>::value)) void k_ozgemm(Gem
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[g][v] = 0;
 
-    if (KC > 0) {
-        gload(0);
-        lstore(0);
-    }
-    __syncthreads();
-    for (int kc = 0; kc < KC; ++kc) {
-        const int buf = kc & 1;
-        if (kc + 1 < KC) gload(kc + 1);
-        v4i fa[S], fb[S];
+    auto compute = [&](int buf) __attribute__((always_inline)) {
+        const uint8_t* sa = &lds[buf][(wm * S) * kFragBytes + lane * 16];
+        const uint8_t* sb = &lds[buf][((4 + wn) * S) * kFragBytes + lane * 16];
+        if constexpr (!FP16) {
+            v4i fb[S];
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            fa[s] = *reinterpret_cast<const v4i*>(&lds[buf][wm][s * kFragBytes + lane * 16]);
-            fb[s] = *reinterpret_cast<const v4i*>(&lds[buf][2 + wn][s * kFragBytes + lane * 16]);
-        }
+            for (int s = 0; s < S; ++s) fb[s] = *reinterpret_cast<const v4i*>(sb + s * kFragBytes);
 #pragma unroll
-        for (int g = 2; g <= S + 1; ++g) {
-            if constexpr (!FP16) {
+            for (int i = 1; i <= S; ++i) {
+                const v4i fa = *reinterpret_cast<const v4i*>(sa + (i - 1) * kFragBytes);
 #pragma unroll
-                for (int i = 1; i < g; ++i) {
-                    const int j = g - i;
-                    if (j <= S)
-                        acc[g - 2] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[i - 1], fb[j - 1],
-                                                                           acc[g - 2], 0, 0, 0);
-                }
-            } else {
+                for (int j = 1; j <= S + 1 - i; ++j)
+                    acc[i + j - 2] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa, fb[j - 1], acc[i + j - 2], 0, 0, 0);
+            }
+        } else {
+            v4i fa[S], fb[S];
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                fa[s] = *reinterpret_cast<const v4i*>(sa + s * kFragBytes);
+                fb[s] = *reinterpret_cast<const v4i*>(sb + s * kFragBytes);
+            }
+#pragma unroll
+            for (int g = 2; g <= S + 1; ++g) {
                 v16f tmp;
 #pragma unroll
                 for (int v = 0; v < 16; ++v) tmp[v] = 0.0f;
@@ -126,21 +148,45 @@ __global__ __launch_bounds__(256, (MinBlocks<S, FP16>::value)) void k_ozgemm(Gem
                 for (int i = 1; i < g; ++i) {
                     const int j = g - i;
                     if (j <= S)
-                        tmp = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                            __builtin_bit_cast(v8h, fa[i - 1]), __builtin_bit_cast(v8h, fb[j - 1]),
-                            tmp, 0, 0, 0);
+                        tmp = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(v8h, fa[i - 1]),
+                                                                     __builtin_bit_cast(v8h, fb[j - 1]),
+                                                                     tmp, 0, 0, 0);
                 }
 #pragma unroll
                 for (int v = 0; v < 16; ++v) acc[g - 2][v] += int(tmp[v]);
             }
         }
-        if (kc + 1 < KC) lstore(buf ^ 1);
-        __syncthreads();
+    };
+
+    v4i r0[PER], r1[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        r0[i] = v4i{0, 0, 0, 0};
+        r1[i] = v4i{0, 0, 0, 0};
+    }
+    // One step for chunk kc (kc = -2, -1 fill the pipeline, kc >= KC drain
+    // it): load chunk min(kc + 2, KC - 1) into the free register set, MFMAs
+    // on chunk kc from LDS buffer ``buf`` when 0 <= kc < KC, store the set
+    // loaded one step earlier (chunk kc + 1) into the other buffer, barrier.
+    // Loads and stores are unconditional (clamped, surplus ones are never
+    // read), so the compiler sees the same loads in flight on every path and
+    // its waits are exact: each store waits only for its own loads, while the
+    // next chunk's loads stay in flight.
+    auto step = [&](int kc, int buf, v4i (&fre)[PER], const v4i (&nxt)[PER]) __attribute__((always_inline)) {
+        gload(min(kc + 2, KC - 1), fre);
+        if (kc >= 0 && kc < KC) compute(buf);
+        lstore(buf ^ 1, nxt);
+        wait_lgkm0();
+        bare_barrier();
+    };
+    for (int kc = -2; kc < KC; kc += 2) {
+        step(kc, 0, r0, r1);
+        step(kc + 1, 1, r1, r0);
     }
 
     // ---- epilogue -----------------------------------------------------------
-    const int col = J * kTile + wn * 32 + (lane & 31);
-    const int row0 = I * kTile + wm * 32 + (lane >> 5) * 4;
+    const int col = J * kTileN + wn * 32 + (lane & 31);
+    const int row0 = I * kTileM + wm * 32 + (lane >> 5) * 4;
     const int fj = d.eb[col];
     const int mode = p.mode;
     double alpha = 0.0, beta = 0.0, gamma = 0.0;
@@ -158,15 +204,14 @@ __global__ __launch_bounds__(256, (MinBlocks<S, FP16>::value)) void k_ozgemm(Gem
 #pragma unroll
         for (int g = S - 2; g >= 0; --g) h = h * 0x1p-8 + double(acc[g][v]);
         const int ei = d.ea[row];
-        double c = (ei >= kNonFiniteExp || fj >= kNonFiniteExp)
-                       ? __builtin_nan("")
-                       : ldexp(h, ei + fj - 2 * kTopBits);
+        const double c = (ei >= kNonFiniteExp || fj >= kNonFiniteExp)
+                             ? __builtin_nan("")
+                             : ldexp(h, ei + fj - 2 * kTopBits);
         if (mode == EPI_STORE) {
             if (row < d.M && col < d.N) d.out[int64_t(row) * d.ldc + col] = c;
             continue;
         }
-        if (row >= n || col >= n) continue;
-        if (I == J && row > col) continue;
+        if (row >= n || col >= n || row > col) continue;
         const bool diag = (row == col);
         const double mult = diag ? 1.0 : 2.0;
         const int64_t ij = int64_t(row) * n + col, ji = int64_t(col) * n + row;
@@ -193,8 +238,14 @@ __global__ __launch_bounds__(256, (MinBlocks<S, FP16>::value)) void k_ozgemm(Gem
         }
         __syncthreads();
         if (tid == 0) {
-            p.partials[int64_t(t) * kPartials + 0] = ((red[0][0] + red[1][0]) + red[2][0]) + red[3][0];
-            p.partials[int64_t(t) * kPartials + 1] = ((red[0][1] + red[1][1]) + red[2][1]) + red[3][1];
+            double r0 = 0.0, r1 = 0.0;
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) {
+                r0 += red[w][0];
+                r1 += red[w][1];
+            }
+            p.partials[int64_t(t) * kPartials + 0] = r0;
+            p.partials[int64_t(t) * kPartials + 1] = r1;
         }
     }
 }
@@ -202,9 +253,9 @@ __global__ __launch_bounds__(256, (MinBlocks<S, FP16>::value)) void k_ozgemm(Gem
 template <int S>
 static void launch_s(bool fp16, const GemmParams& p, int ntiles, hipStream_t stream) {
     if (fp16)
-        k_ozgemm<S, true><<<ntiles, 256, 0, stream>>>(p);
+        k_ozgemm<S, true><<<ntiles, kGemmThreads, 0, stream>>>(p);
     else
-        k_ozgemm<S, false><<<ntiles, 256, 0, stream>>>(p);
+        k_ozgemm<S, false><<<ntiles, kGemmThreads, 0, stream>>>(p);
 }
 
 using GemmFn = void (*)(bool, const GemmParams&, int, hipStream_t);

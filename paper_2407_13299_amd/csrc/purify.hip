@@ -364,10 +364,7 @@ int native_pairs(int n) {
     const int t = (n + 31) / 32;
     return t * (t + 1) / 2;
 }
-int oz_tiles(int n) {
-    const int t = int(round_up(n, kTile) / kTile);
-    return t * (t + 1) / 2;
-}
+int oz_tiles(int n) { return upper_tile_count(n); }
 
 MatLayout carve_matrix(Carver& c, int n, int S, dmp_kind kind) {
     MatLayout m{};
@@ -472,8 +469,7 @@ int upload_group(GroupPlan& g, const double* const* H, double* const* P, const i
             d.part_begin = pbeg;
             pbeg += oz_tiles(nb);
             d.part_end = pbeg;
-            append_tiles(tiles, int(round_up(nb, kTile) / kTile), int(round_up(nb, kTile) / kTile),
-                         true, uint32_t(b));
+            append_tiles(tiles, tile_rows(nb), tile_cols(nb), true, uint32_t(b));
         }
         pd[b] = d;
         if (g.kind == DMP_FP64_NATIVE) continue;
@@ -779,7 +775,7 @@ int validate_purify_args(const double* H, int n, int nocc, double tol, int max_i
         set_error("H and P must be distinct non-null device pointers");
         return DMP_EINVAL;
     }
-    if (n > 65535 * kTile) {
+    if (n > 65535 * kTileN) {
         set_error("n too large");
         return DMP_EINVAL;
     }
