@@ -41,7 +41,32 @@ def parse():
     ap.add_argument("--native-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-native", action="store_true")
+    ap.add_argument("--max-iter", type=int, default=200,
+                    help="iteration cap (short profiled runs use a few)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run one plain device copy of MIB MiB (counter calibration)")
     return ap.parse_args()
+
+
+def profiled_traffic(kind, slices, which="update"):
+    """HBM bytes per launch of the slice GEMM from the committed rocprofv3
+    counter summary, or None when that summary was taken on another version
+    of the kernel source (or for another configuration)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_ozgemm_{kind}_s{slices}_tb8192_traffic.md")
+    src = os.path.join(ROOT, "paper_2407_13299_amd", "csrc", "ozgemm.hip")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if " = " in line:
+            k, v = line.split(" = ", 1)
+            vals[k.strip()] = v.strip()
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if vals.get("source_sha256") != digest:
+        return None
+    v = vals.get(f"{which}_traffic_bytes")
+    return float(v) if v is not None else None
 
 
 def cpu_baseline(h, nocc, iters=2):
@@ -64,12 +89,64 @@ def cpu_baseline(h, nocc, iters=2):
                        f"{dt:.1f} s")
 
 
+def bench_batched(a):
+    """64 spectrum-controlled Hamiltonians, n ~ U{128..1536}, purified together."""
+    import torch
+    import paper_2407_13299_amd as dmp
+    from paper_2407_13299_amd.workloads import workload
+
+    w = workload("batched_64")
+    hs = [torch.from_numpy(h).cuda() for h in w["H"]]
+    noccs = w["nocc"]
+    ns = [h.shape[0] for h in hs]
+
+    def run(kind, slices):
+        return dmp.purify_batched(hs, noccs, tol=w["tol"], slices=slices, kind=kind,
+                                  max_iter=a.max_iter)
+
+    for _ in range(a.warmup):
+        run(a.kind, a.slices)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        _, es, infos = run(a.kind, a.slices)
+        torch.cuda.synchronize()
+        print(f"# step {k} done", file=sys.stderr, flush=True)
+    ms = (time.perf_counter() - t0) / a.steps * 1e3
+    flops = sum(i["iters"] * 4.0 * n ** 3 for i, n in zip(infos, ns))
+    native = None
+    if not a.no_native:
+        run("native", 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, infn = run("native", 0)
+        torch.cuda.synchronize()
+        msn = (time.perf_counter() - t0) * 1e3
+        native = dict(ms=msn, tflops_fp64_equiv=sum(i["iters"] * 4.0 * n ** 3
+                                                    for i, n in zip(infn, ns)) / msn / 1e9,
+                      speedup_ozaki_vs_native=msn / ms)
+    line = {"metric": "batched purification time & FP64-equiv TFLOP/s (64 H, n~U{128..1536})",
+            "value": flops / (ms / 1e3) / 1e12, "unit": "TFLOP/s (FP64-equivalent)",
+            "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "i8" if a.kind == "int8" else "f16", "data": "synthetic",
+            "config": {"workload": "batched_64", "count": len(hs), "sum_n3": sum(n ** 3 for n in ns),
+                       "slices": [i["slices"] for i in infos][:4] + ["..."],
+                       "iters_min_max": [min(i["iters"] for i in infos), max(i["iters"] for i in infos)],
+                       "all_converged": all(i["stop"] == "converged" for i in infos)},
+            "native_fp64": native}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU "
                                    "sharding is described in DESIGN.md but not built"}))
         sys.exit(2)
+    if a.workload == "batched_64":
+        bench_batched(a)
+        return
     import torch
     import paper_2407_13299_amd as dmp
     from paper_2407_13299_amd import _lib
@@ -86,7 +163,18 @@ def main():
                      device="cuda")
 
     def run(kind, slices, out, wsb):
-        return dmp.purify(H, nocc, tol=tol, slices=slices, kind=kind, out=out, workspace=wsb)
+        return dmp.purify(H, nocc, tol=tol, slices=slices, kind=kind, out=out, workspace=wsb,
+                          max_iter=a.max_iter)
+
+    if a.calibrate_copy:
+        src = torch.empty(a.calibrate_copy << 20, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# calibration copy: {a.calibrate_copy} MiB read + written", file=sys.stderr,
+              flush=True)
+        del src, dst
 
     print(f"# workload {a.workload}: n={n} nocc={nocc}; warmup {a.warmup}", file=sys.stderr,
           flush=True)
@@ -189,7 +277,11 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "k_ozgemm (update: X2 P, upper triangle)",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "ops": "int8 multiply-adds counted as 2 ops" if a.kind == "int8" else "fp16",
-                     "frac": achieved / peak if peak else None, "traffic": None,
+                     "frac": achieved / peak if peak else None,
+                     "traffic": (profiled_traffic(a.kind, a.slices) if a.workload == "tb_8192"
+                                 else None),
+                     "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE/WRITE_SIZE, "
+                                     "copy-calibrated)",
                      "kernels": kernels},
         "native_fp64": native,
         "cpu_baseline": cpu,

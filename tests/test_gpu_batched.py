@@ -1,0 +1,91 @@
+"""Batched purification (one grouped launch per phase, hipGraph replay)."""
+import numpy as np
+import pytest
+
+from oracle import projector
+from paper_2407_13299_amd.workloads import (batched_spectrum_sizes,
+                                            spectrum_hamiltonian,
+                                            tight_binding_hamiltonian)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+dmp = pytest.importorskip("paper_2407_13299_amd")
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def make_batch(sizes, seed0=100):
+    hs, noccs = [], []
+    for b, n in enumerate(sizes):
+        nocc = n // 2
+        h, _, _ = spectrum_hamiltonian(n, nocc, seed=seed0 + b)
+        hs.append(h)
+        noccs.append(nocc)
+    return hs, noccs
+
+
+@pytest.mark.parametrize("kind", ["int8", "fp16"])
+def test_batched_equals_single_bitwise(kind):
+    sizes = [100, 128, 300, 64, 513, 2, 1]
+    hs, noccs = make_batch(sizes)
+    Ps, Es, infos = dmp.purify_batched([dev(h) for h in hs], noccs, tol=1e-10, slices=7,
+                                       kind=kind)
+    torch.cuda.synchronize()
+    for h, nocc, p, e, info in zip(hs, noccs, Ps, Es, infos):
+        p1, e1, i1 = dmp.purify(dev(h), nocc, tol=1e-10, slices=7, kind=kind)
+        torch.cuda.synchronize()
+        assert torch.equal(p, p1) and e == e1 and info["iters"] == i1["iters"]
+        p_ref, e_ref, _, _ = projector.eigh_projector(h, nocc)
+        assert np.max(np.abs(p.cpu().numpy() - p_ref)) < 1e-10
+        assert abs(e - e_ref) < 1e-8
+
+
+def test_batched_autotuned_slices_and_mixed_models():
+    hs = [tight_binding_hamiltonian(4, 4, 4, seed=1), tight_binding_hamiltonian(3, 4, 5, seed=2)]
+    noccs = [64, 60]
+    h3, _, _ = spectrum_hamiltonian(700, 350, seed=9)
+    hs.append(h3)
+    noccs.append(350)
+    Ps, Es, infos = dmp.purify_batched([dev(h) for h in hs], noccs, tol=1e-9, slices=0)
+    torch.cuda.synchronize()
+    for h, nocc, p, e, info in zip(hs, noccs, Ps, Es, infos):
+        assert info["slices"] == dmp.autotune_slices(h.shape[0], 1e-10)
+        assert info["stop"] == "converged"
+        p_ref, e_ref, _, _ = projector.eigh_projector(h, nocc)
+        assert np.max(np.abs(p.cpu().numpy() - p_ref)) < 1e-10
+        assert abs(e - e_ref) < 1e-8
+
+
+def test_batched_workload_sample():
+    """Eight matrices of the 64-matrix workload (sizes from its generator)."""
+    sizes = [int(s) for s in batched_spectrum_sizes(64, seed=3)[:8]]
+    hs = [spectrum_hamiltonian(n, n // 2, seed=1000 + b)[0] for b, n in enumerate(sizes)]
+    noccs = [n // 2 for n in sizes]
+    Ps, Es, infos = dmp.purify_batched([dev(h) for h in hs], noccs, tol=1e-8, slices=7)
+    torch.cuda.synchronize()
+    for h, nocc, p, e, info in zip(hs, noccs, Ps, Es, infos):
+        p_ref, e_ref, _, _ = projector.eigh_projector(h, nocc)
+        assert np.max(np.abs(p.cpu().numpy() - p_ref)) < 1e-10
+        assert abs(e - e_ref) < 1e-8
+
+
+def test_batched_reports_not_converged():
+    hs, noccs = make_batch([96, 80])
+    Ps, Es, infos = dmp.purify_batched([dev(h) for h in hs], noccs, tol=1e-10, slices=7,
+                                       max_iter=3)
+    torch.cuda.synchronize()
+    assert all(i["stop"] == "max_iter" and i["iters"] == 3 for i in infos)
+
+
+def test_batched_gemm_grouped_equals_single():
+    rng = np.random.default_rng(3)
+    shapes = [(200, 130, 70), (64, 64, 64), (129, 257, 33)]
+    As = [rng.standard_normal((m, k)) for m, n, k in shapes]
+    Bs = [rng.standard_normal((k, n)) for m, n, k in shapes]
+    Cs = dmp.ozaki_gemm_batched([dev(a) for a in As], [dev(b) for b in Bs], slices=7)
+    for a, b, c in zip(As, Bs, Cs):
+        c1 = dmp.ozaki_gemm(dev(a), dev(b), slices=7)
+        torch.cuda.synchronize()
+        assert torch.equal(c, c1)
