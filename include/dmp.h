@@ -171,8 +171,10 @@ int dmp_autotune_slices(int n, double target, dmp_kind kind);
 /* ---------------------------------------------------------------------
  * Adjoint of the purification (reverse mode).  dmp_purify_fwd_tape runs
  * dmp_purify and records, for every iteration, the branch, c and the
- * traces, plus the iterate P_k for every k that is a multiple of
- * ckpt_stride (ckpt_stride >= 1), in memory owned by the tape.
+ * traces, plus a copy of H and the iterate P_k for every k that is a
+ * multiple of ckpt_stride (ckpt_stride <= 0 picks ceil(sqrt(max_iter))),
+ * in device memory owned by the tape (allocated here, released by
+ * dmp_tape_free).  Only the Ozaki kinds are supported.
  * dmp_purify_bwd takes Pbar = dL/dP (device, symmetric n x n; for
  * L = tr(P W) it is W) and writes Hbar = dL/dH (device, symmetric), the
  * derivative of the recorded iteration (fixed branch pattern) including the
@@ -191,6 +193,9 @@ int dmp_purify_bwd(const dmp_tape* tape, const double* Pbar, double* Hbar,
                    void* ws, size_t ws_bytes, void* stream);
 /* Number of iterations and branch of each (host array of length >= iters). */
 int dmp_tape_info(const dmp_tape* tape, int* iters, int* branches);
+/* Recorded c_k, tr(P_k - P_k^2) and tr(P_k^2 - P_k^3) of every iteration
+ * (host arrays of length >= iters; any may be NULL). */
+int dmp_tape_coefficients(const dmp_tape* tape, double* c, double* t1, double* t2);
 void dmp_tape_free(dmp_tape* tape);
 
 /* ---------------------------------------------------------------------

@@ -22,7 +22,7 @@ EXPORTS = [
     "dmp_purify_batched_workspace_bytes", "dmp_purify_batched",
     "dmp_autotune_slices",
     "dmp_purify_fwd_tape", "dmp_purify_bwd_workspace_bytes", "dmp_purify_bwd",
-    "dmp_tape_info", "dmp_tape_free",
+    "dmp_tape_info", "dmp_tape_coefficients", "dmp_tape_free",
     "dmp_timing_enable", "dmp_timing_reset", "dmp_timing_read",
 ]
 
@@ -77,6 +77,7 @@ _SIGS = {
     "dmp_purify_bwd": (_I, [_P, _P, _P, _P, _SZ, _P]),
     "dmp_tape_info": (_I, [_P, _IP, _IP]),
     "dmp_tape_free": (None, [_P]),
+    "dmp_tape_coefficients": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "dmp_timing_enable": (None, [_I]),
     "dmp_timing_reset": (None, []),
     "dmp_timing_read": (_I, [_I, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong),

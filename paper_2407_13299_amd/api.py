@@ -164,6 +164,7 @@ class PurifyTape:
         n = H.shape[0]
         self.n = n
         self.device = H.device
+        self.H = H          # the library copies H, this only keeps the caller's alive
         self.P = torch.empty_like(H)
         e = ctypes.c_double(0.0)
         info = _lib.DmpInfo()
@@ -183,6 +184,14 @@ class PurifyTape:
         br = (ctypes.c_int * max(1, it.value))()
         lib.dmp_tape_info(self._tape, ctypes.byref(it), br)
         return list(br)[: it.value]
+
+    def coefficients(self):
+        """Recorded (c_k, t1_k, t2_k) of every iteration, as lists."""
+        lib = _lib.load()
+        k = self.info["iters"]
+        arr = [(ctypes.c_double * max(1, k))() for _ in range(3)]
+        lib.dmp_tape_coefficients(self._tape, arr[0], arr[1], arr[2])
+        return [list(a)[:k] for a in arr]
 
     def backward(self, Pbar, stream=None):
         lib = _lib.load()

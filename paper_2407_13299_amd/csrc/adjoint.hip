@@ -1,34 +1,693 @@
-// Adjoint of the purification sequence (placeholder until the reverse pass
-// lands): every entry point reports DMP_EUNSUPPORTED.
+// Reverse-mode derivative of the canonical purification (dL/dH for a scalar L
+// of the converged density matrix; for L = tr(P W) the seed is W).
+//
+// Forward with tape: the same kernels as dmp_purify, one iteration at a time;
+// for every iteration k the tape keeps c_k, its branch, t1 = tr(P - P^2),
+// t2 = tr(P^2 - P^3) and whether c_k was clamped, and it keeps P_k for every
+// k that is a multiple of the checkpoint stride.
+//
+// Backward, for k = K-1 .. 0 (segments of ``stride`` iterations are first
+// recomputed from their checkpoint with the same deterministic products, so
+// the recomputed iterates equal the forward ones bit for bit).  With Y the
+// adjoint of P_{k+1} (symmetric), P = P_k, X2 = P_k^2 and the update
+// P_{k+1} = a P + b P^2 + g P^3 on the recorded branch:
+//   M = Y P,  MP = M P (= Y P^2),  PM = P M (= P Y P)        (3 Ozaki GEMMs)
+//   cbar = a' <Y, P> + b' <Y, P^2> + g' <Y, P^3>,  <Y, P^3> = sum MP o P
+//   Y <- a Y + b (M + M^T) + g (MP + MP^T + (PM + PM^T) / 2)
+//        + cbar ((2P - 3X2) t1 - t2 (I - 2P)) / t1^2     (no cbar if clamped)
+// and finally, for P0 = lam (mu I - H) + theta I with mu = tr H / n and lam
+// from the Gershgorin bounds (the extremal row held fixed):
+//   Hbar = sym(-lam Y + (lam tr Y / n) I + lambar dlam/dH),
+//   lambar = mu tr Y - <Y, H>.
+// This is the derivative of the recorded iteration (fixed branch pattern),
+// the quantity the finite-difference and perturbation-theory checks compare.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
 #include "host.hpp"
+
+namespace dmp {
+namespace {
+
+constexpr int kDotBlocks = 256;
+
+// Single-matrix Ozaki context: device buffers for one split pair and the
+// purification state of one matrix.
+struct OzCtx {
+    int n = 0, S = 0, KC = 0;
+    dmp_kind kind = DMP_OZ_INT8;
+    int64_t rb_stride = 0;
+    const double* H = nullptr;
+    uint8_t* pa = nullptr;
+    uint8_t* pb = nullptr;
+    int* ea = nullptr;
+    int* eb = nullptr;
+    uint64_t* ma = nullptr;
+    uint64_t* mb = nullptr;
+    double* partials = nullptr;
+    double* rows = nullptr;
+    int* rowbad = nullptr;
+    double* e0 = nullptr;
+    double* dots = nullptr;     // [kDotBlocks][4]
+    double* scal = nullptr;     // [8] device scalars
+    PurDesc* pd = nullptr;
+    DevState* st = nullptr;
+    const Tile* tiles_up = nullptr;
+    int nt_up = 0;
+    const Tile* tiles_full = nullptr;
+    int nt_full = 0;
+};
+
+void carve_ctx(Carver& c, OzCtx& x, int n, int S, dmp_kind kind) {
+    x.n = n;
+    x.S = S;
+    x.kind = kind;
+    x.KC = int(chunks_of(n, kind));
+    x.rb_stride = int64_t(x.KC) * S * kFragBytes;
+    x.pa = c.take<uint8_t>(plane_bytes(n, n, S, kind));
+    x.pb = c.take<uint8_t>(plane_bytes(n, n, S, kind));
+    x.ea = c.take<int>(round_up(n, kPad));
+    x.eb = c.take<int>(round_up(n, kPad));
+    x.ma = c.take<uint64_t>(round_up(n, kPad));
+    x.mb = c.take<uint64_t>(round_up(n, kPad));
+    x.partials = c.take<double>(size_t(std::max(upper_tile_count(n), 1)) * kPartials);
+    x.rows = c.take<double>(3 * size_t(n));
+    x.rowbad = c.take<int>(n);
+    x.e0 = c.take<double>(e0_blocks());
+    x.dots = c.take<double>(kDotBlocks * 4);
+    x.scal = c.take<double>(8);
+    x.pd = c.take<PurDesc>(1);
+    x.st = c.take<DevState>(1);
+}
+
+int bind_ctx(OzCtx& x, const double* H, int nocc, double* P0, hipStream_t s) {
+    x.H = H;
+    const int tm = tile_rows(x.n), tn = tile_cols(x.n);
+    DMP_CHECK(cached_tiles(tm, tn, true, &x.tiles_up));
+    DMP_CHECK(cached_tiles(tm, tn, false, &x.tiles_full));
+    x.nt_up = upper_tile_count(x.n);
+    x.nt_full = tm * tn;
+    PurDesc d{};
+    d.H = H;
+    d.Pb[0] = P0;
+    d.Pb[1] = P0;
+    d.rows = x.rows;
+    d.rowbad = x.rowbad;
+    d.e0 = x.e0;
+    d.partials = x.partials;
+    d.n = x.n;
+    d.nocc = nocc;
+    d.part_begin = 0;
+    d.part_end = x.nt_up;
+    DMP_CHECK_HIP(hipMemcpyAsync(x.pd, &d, sizeof(d), hipMemcpyHostToDevice, s));
+    DMP_CHECK_HIP(hipStreamSynchronize(s));
+    return DMP_OK;
+}
+
+SplitDesc split_of(const OzCtx& x, const double* A, bool trans, uint64_t* mb, int* ex,
+                   uint8_t* planes, int state_index) {
+    SplitDesc d{};
+    d.A = A;
+    d.lda = x.n;
+    d.R = x.n;
+    d.K = x.n;
+    d.trans = trans ? 1 : 0;
+    d.KC = x.KC;
+    d.maxbits = mb;
+    d.expo = ex;
+    d.planes = planes;
+    d.state_index = state_index;
+    return d;
+}
+
+MatDesc gemm_desc(const OzCtx& x, const uint8_t* pa, const int* ea, const uint8_t* pb,
+                  const int* eb, double* out) {
+    MatDesc m{};
+    m.pa = pa;
+    m.pb = pb;
+    m.ea = ea;
+    m.eb = eb;
+    m.out = out;
+    m.a_rb_stride = x.rb_stride;
+    m.b_rb_stride = x.rb_stride;
+    m.M = x.n;
+    m.N = x.n;
+    m.KC = x.KC;
+    m.ldc = x.n;
+    m.state_index = 0;
+    return m;
+}
+
+// One forward iteration P_in -> (X2_out, P_out) with the purification
+// kernels; the coefficient is recomputed on the device from the traces.
+int forward_iteration(const OzCtx& x, const double* P_in, double* X2_out, double* P_out,
+                      bool finalize, hipStream_t s) {
+    DMP_CHECK(launch_split(split_of(x, P_in, false, x.ma, x.ea, x.pa, 0), x.S, x.kind, x.st, s));
+    GemmParams p{};
+    p.tiles = x.tiles_up;
+    p.one = gemm_desc(x, x.pa, x.ea, x.pa, x.ea, X2_out);
+    p.one.P = P_in;
+    p.partials = x.partials;
+    p.states = x.st;
+    p.mode = EPI_SQUARE;
+    DMP_CHECK(launch_ozgemm(x.S, x.kind, p, x.nt_up, s));
+    DMP_CHECK(launch_finalize_coef(x.pd, x.st, 1, s));
+    DMP_CHECK(launch_split(split_of(x, X2_out, false, x.mb, x.eb, x.pb, 0), x.S, x.kind, x.st, s));
+    p.one = gemm_desc(x, x.pb, x.eb, x.pa, x.ea, P_out);
+    p.one.P = P_in;
+    p.one.X2 = X2_out;
+    p.one.H = x.H;
+    p.mode = EPI_UPDATE;
+    DMP_CHECK(launch_ozgemm(x.S, x.kind, p, x.nt_up, s));
+    if (finalize) DMP_CHECK(launch_finalize_iter(x.pd, x.st, 1, s));
+    return DMP_OK;
+}
+
+// C = A B for n x n operands already split: (pa, ea) rows of A, (pb, eb)
+// columns of B.
+int gemm_store(const OzCtx& x, const uint8_t* pa, const int* ea, const uint8_t* pb,
+               const int* eb, double* out, hipStream_t s) {
+    GemmParams p{};
+    p.tiles = x.tiles_full;
+    p.one = gemm_desc(x, pa, ea, pb, eb, out);
+    p.one.state_index = -1;
+    p.mode = EPI_STORE;
+    return launch_ozgemm(x.S, x.kind, p, x.nt_full, s);
+}
+
+__device__ inline double wsum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ inline double bsum(double v, double* sh) {
+    v = wsum(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const double r = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+    __syncthreads();
+    return r;
+}
+
+// Y = (A + A^T) / 2 on 32 x 32 tile pairs (I <= J), through LDS.
+__global__ __launch_bounds__(256) void k_sym(const double* A, double* Y, int n, const int2* pairs) {
+    __shared__ double t[32][33];
+    const int2 pr = pairs[blockIdx.x];
+    const int I = pr.x, J = pr.y, tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int r = ty; r < 32; r += 8) {
+        const int i = J * 32 + r, j = I * 32 + tx;
+        t[r][tx] = (i < n && j < n) ? A[int64_t(i) * n + j] : 0.0;   // tile (J, I)
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int i = I * 32 + r, j = J * 32 + tx;
+        if (i < n && j < n) {
+            const double v = 0.5 * (A[int64_t(i) * n + j] + t[tx][r]);
+            Y[int64_t(i) * n + j] = v;
+            Y[int64_t(j) * n + i] = v;
+        }
+    }
+}
+
+// Block partials of sum Y o P, sum Y o X2, sum MP o P (fixed grid).
+__global__ __launch_bounds__(256) void k_adj_dots(const double* Y, const double* P,
+                                                  const double* X2, const double* MP, int n,
+                                                  double* out) {
+    __shared__ double sh[4];
+    const int64_t tot = int64_t(n) * n;
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < tot; i += int64_t(kDotBlocks) * 256) {
+        const double y = Y[i], p = P[i];
+        a += y * p;
+        b += y * X2[i];
+        c += MP[i] * p;
+    }
+    a = bsum(a, sh);
+    b = bsum(b, sh);
+    c = bsum(c, sh);
+    if (threadIdx.x == 0) {
+        out[blockIdx.x * 4 + 0] = a;
+        out[blockIdx.x * 4 + 1] = b;
+        out[blockIdx.x * 4 + 2] = c;
+    }
+}
+
+// cbar of one step from the dot partials and the recorded c, branch.
+__global__ __launch_bounds__(256) void k_adj_cbar(const double* dots, double c, int branch,
+                                                  int clamped, double* scal) {
+    __shared__ double sh[4];
+    double a = 0.0, b = 0.0, g = 0.0;
+    for (int i = threadIdx.x; i < kDotBlocks; i += 256) {
+        a += dots[i * 4 + 0];
+        b += dots[i * 4 + 1];
+        g += dots[i * 4 + 2];
+    }
+    a = bsum(a, sh);
+    b = bsum(b, sh);
+    g = bsum(g, sh);
+    if (threadIdx.x == 0) {
+        double cbar = 0.0;
+        if (!clamped) {
+            if (branch) {
+                cbar = (-b + g) / (c * c);            // beta' = -1/c^2, gamma' = 1/c^2
+            } else {
+                const double q = (1.0 - c) * (1.0 - c);
+                cbar = (-a + 2.0 * b - g) / q;        // alpha' = -1/q, beta' = 2/q, gamma' = -1/q
+            }
+        }
+        scal[0] = cbar;
+    }
+}
+
+// Y' = a Y + b (M + M^T) + g (MP + MP^T + (PM + PM^T)/2) + cbar dc, on tile
+// pairs (I <= J); symmetric, written to both tiles.
+__global__ __launch_bounds__(256) void k_adj_combine(const double* Y, const double* M,
+                                                     const double* MP, const double* PM,
+                                                     const double* P, const double* X2,
+                                                     double* Yn, int n, double a, double b,
+                                                     double g, double t1, double t2,
+                                                     const double* scal, const int2* pairs) {
+    __shared__ double tM[32][33], tMP[32][33], tPM[32][33], tO[32][33];
+    const int2 pr = pairs[blockIdx.x];
+    const int I = pr.x, J = pr.y, tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const double cbar = scal[0];
+    const double inv = (cbar != 0.0) ? 1.0 / (t1 * t1) : 0.0;
+    for (int r = ty; r < 32; r += 8) {      // tile (J, I) of M, MP, PM
+        const int i = J * 32 + r, j = I * 32 + tx;
+        const bool ok = i < n && j < n;
+        const int64_t o = int64_t(i) * n + j;
+        tM[r][tx] = ok ? M[o] : 0.0;
+        tMP[r][tx] = ok ? MP[o] : 0.0;
+        tPM[r][tx] = ok ? PM[o] : 0.0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int i = I * 32 + r, j = J * 32 + tx;
+        double v = 0.0;
+        if (i < n && j < n) {
+            const int64_t o = int64_t(i) * n + j;
+            const double p = P[o], x2 = X2[o];
+            v = a * Y[o] + b * (M[o] + tM[tx][r]) + g * (MP[o] + tMP[tx][r] + 0.5 * (PM[o] + tPM[tx][r]));
+            if (cbar != 0.0) v += cbar * ((2.0 * p - 3.0 * x2) * t1 - t2 * ((i == j ? 1.0 : 0.0) - 2.0 * p)) * inv;
+            Yn[o] = v;
+        }
+        tO[r][tx] = v;
+    }
+    __syncthreads();
+    if (I != J) {
+        for (int r = ty; r < 32; r += 8) {
+            const int i = J * 32 + r, j = I * 32 + tx;
+            if (i < n && j < n) Yn[int64_t(i) * n + j] = tO[tx][r];
+        }
+    }
+}
+
+// Partials of tr Y and <Y, H>.
+__global__ __launch_bounds__(256) void k_adj_dots0(const double* Y, const double* H, int n,
+                                                   double* out) {
+    __shared__ double sh[4];
+    const int64_t tot = int64_t(n) * n;
+    double tr = 0.0, yh = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < tot; i += int64_t(kDotBlocks) * 256) {
+        yh += Y[i] * H[i];
+        if (i / n == i % n) tr += Y[i];
+    }
+    tr = bsum(tr, sh);
+    yh = bsum(yh, sh);
+    if (threadIdx.x == 0) {
+        out[blockIdx.x * 4 + 0] = tr;
+        out[blockIdx.x * 4 + 1] = yh;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_adj_scal0(const double* dots, double* scal) {
+    __shared__ double sh[4];
+    double tr = 0.0, yh = 0.0;
+    for (int i = threadIdx.x; i < kDotBlocks; i += 256) {
+        tr += dots[i * 4 + 0];
+        yh += dots[i * 4 + 1];
+    }
+    tr = bsum(tr, sh);
+    yh = bsum(yh, sh);
+    if (threadIdx.x == 0) {
+        scal[1] = tr;
+        scal[2] = yh;
+    }
+}
+
+// Hbar from the adjoint of P0 (see the header of this file).
+__global__ __launch_bounds__(256) void k_adj_initial(const double* Y, const double* H, double* Hbar,
+                                                     int n, double lam, double mu, double theta,
+                                                     double h_min, double h_max, int which, int rmax,
+                                                     int rmin, const double* scal) {
+    const int64_t tot = int64_t(n) * n;
+    const double trY = scal[1], yh = scal[2];
+    const double lambar = mu * trY - yh;
+    const int r = which == 0 ? rmax : rmin;
+    const double sg = which == 0 ? 1.0 : -1.0;
+    const double kap = which == 0 ? -theta / ((h_max - mu) * (h_max - mu))
+                                  : -(1.0 - theta) / ((mu - h_min) * (mu - h_min));
+    for (int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x; idx < tot;
+         idx += int64_t(gridDim.x) * 256) {
+        const int i = int(idx / n), j = int(idx % n);
+        const double dij = i == j ? 1.0 : 0.0;
+        auto gent = [&](int a, int b) -> double {
+            if (a != r) return 0.0;
+            if (b == r) return 1.0;
+            const double h = H[int64_t(r) * n + b];
+            return sg * (h > 0.0 ? 1.0 : (h < 0.0 ? -1.0 : 0.0));
+        };
+        const double gs = 0.5 * (gent(i, j) + gent(j, i));
+        const double dl = which == 0 ? (gs - dij / n) : (dij / n - gs);
+        double v = -lam * Y[idx] + dij * lam * trY / n;
+        if (lam != 0.0) v += lambar * kap * dl;
+        Hbar[idx] = v;
+    }
+}
+
+std::vector<int2> tile_pairs32(int n) {
+    std::vector<int2> v;
+    const int t = (n + 31) / 32;
+    for (int i = 0; i < t; ++i)
+        for (int j = i; j < t; ++j) v.push_back(int2{i, j});
+    return v;
+}
+
+}  // namespace
+}  // namespace dmp
 
 using namespace dmp;
 
 struct dmp_tape {
-    int n;
+    int n = 0, nocc = 0, S = 0, stride = 1, K = 0, device = 0;
+    dmp_kind kind = DMP_OZ_INT8;
+    const double* H = nullptr;
+    DevState init{};
+    std::vector<double> c, t1, t2;
+    std::vector<int> branch, clamped;
+    std::vector<double*> ckpt;   // device copies of P_0, P_stride, ...
+    void* fwd_ws = nullptr;      // forward workspace (owned)
+    double* H_copy = nullptr;    // tape-owned copy of H (the caller's may change)
 };
 
 extern "C" {
 
-int dmp_purify_fwd_tape(const double*, int, int, double, int, dmp_kind, int, int, double*,
-                        double*, dmp_info*, dmp_tape** tape, void*) {
-    if (tape) *tape = nullptr;
-    set_error("adjoint not built");
-    return DMP_EUNSUPPORTED;
+void dmp_tape_free(dmp_tape* t) {
+    if (!t) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(t->device);
+    for (double* p : t->ckpt) (void)hipFree(p);
+    if (t->fwd_ws) (void)hipFree(t->fwd_ws);
+    if (t->H_copy) (void)hipFree(t->H_copy);
+    (void)hipSetDevice(cur);
+    delete t;
 }
 
-size_t dmp_purify_bwd_workspace_bytes(const dmp_tape*) { return 0; }
-
-int dmp_purify_bwd(const dmp_tape*, const double*, double*, void*, size_t, void*) {
-    set_error("adjoint not built");
-    return DMP_EUNSUPPORTED;
+int dmp_tape_info(const dmp_tape* t, int* iters, int* branches) {
+    if (!t) {
+        set_error("null tape");
+        return DMP_EINVAL;
+    }
+    if (iters) *iters = t->K;
+    if (branches)
+        for (int k = 0; k < t->K; ++k) branches[k] = t->branch[k];
+    return DMP_OK;
 }
 
-int dmp_tape_info(const dmp_tape*, int* iters, int*) {
-    if (iters) *iters = 0;
-    return DMP_EUNSUPPORTED;
+int dmp_tape_coefficients(const dmp_tape* t, double* c, double* t1, double* t2) {
+    if (!t) {
+        set_error("null tape");
+        return DMP_EINVAL;
+    }
+    for (int k = 0; k < t->K; ++k) {
+        if (c) c[k] = t->c[k];
+        if (t1) t1[k] = t->t1[k];
+        if (t2) t2[k] = t->t2[k];
+    }
+    return DMP_OK;
 }
 
-void dmp_tape_free(dmp_tape* t) { delete t; }
+int dmp_purify_fwd_tape(const double* H, int n, int nocc, double tol, int slices, dmp_kind kind,
+                        int max_iter, int ckpt_stride, double* P, double* E, dmp_info* info,
+                        dmp_tape** tape, void* stream) {
+    clear_error();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!tape) {
+        set_error("tape pointer is null");
+        return DMP_EINVAL;
+    }
+    *tape = nullptr;
+    {
+        const hipError_t pending = hipGetLastError();
+        if (pending != hipSuccess) {
+            set_error("a previous HIP call failed: %s", hipGetErrorString(pending));
+            return DMP_EHIP;
+        }
+    }
+    DMP_CHECK(check_kind_slices(kind, slices));
+    if (kind == DMP_FP64_NATIVE) {
+        set_error("the recorded adjoint is built for the Ozaki kinds");
+        return DMP_EUNSUPPORTED;
+    }
+    DMP_CHECK(validate_purify_args(H, n, nocc, tol, max_iter, P));
+    if (n > max_k_for_slices(slices)) {
+        set_error("n = %d exceeds the exact INT32 range for %d slices", n, slices);
+        return DMP_EINVAL;
+    }
+    const int stride = ckpt_stride > 0 ? ckpt_stride
+                                       : std::max(1, int(std::ceil(std::sqrt(double(max_iter)))));
+    dmp_tape* t = new dmp_tape();
+    t->n = n;
+    t->nocc = nocc;
+    t->S = slices;
+    t->kind = kind;
+    t->stride = stride;
+    (void)hipGetDevice(&t->device);
+    // the backward pass reads H again: keep a copy owned by the tape
+    if (hipMalloc(&t->H_copy, size_t(n) * n * sizeof(double)) != hipSuccess ||
+        hipMemcpyAsync(t->H_copy, H, size_t(n) * n * sizeof(double), hipMemcpyDefault, s) != hipSuccess) {
+        set_error("copy of H into the tape failed");
+        dmp_tape_free(t);
+        return DMP_ENOMEM;
+    }
+    t->H = t->H_copy;
+
+    // measure with exactly the takes used below (alignment padding included)
+    Carver m(nullptr);
+    OzCtx probe;
+    carve_ctx(m, probe, n, slices, kind);
+    m.take<double>(size_t(n) * n);   // X2
+    m.take<double>(size_t(n) * n);   // second iterate
+    const size_t need = m.used();
+    if (hipMalloc(&t->fwd_ws, need) != hipSuccess) {
+        set_error("hipMalloc of %zu bytes for the forward tape failed", need);
+        dmp_tape_free(t);
+        return DMP_ENOMEM;
+    }
+    Carver c(t->fwd_ws);
+    OzCtx x;
+    carve_ctx(c, x, n, slices, kind);
+    double* X2 = c.take<double>(size_t(n) * n);
+    double* Pw = c.take<double>(size_t(n) * n);
+    int st = bind_ctx(x, t->H, nocc, P, s);
+    if (st == DMP_OK) st = launch_purify_init(x.pd, x.st, 1, n, tol, max_iter, s);
+    DevState h{};
+    if (st == DMP_OK && (hipMemcpyAsync(&h, x.st, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                         hipStreamSynchronize(s) != hipSuccess)) {
+        set_error("state readback failed");
+        st = DMP_EHIP;
+    }
+    if (st == DMP_OK && h.nonfinite) {
+        set_error("H holds a non-finite entry");
+        st = DMP_ENONFINITE;
+    }
+    if (st != DMP_OK) {
+        dmp_tape_free(t);
+        return st;
+    }
+    t->init = h;
+    auto checkpoint = [&](const double* src) -> int {
+        double* d = nullptr;
+        if (hipMalloc(&d, size_t(n) * n * sizeof(double)) != hipSuccess) {
+            set_error("hipMalloc of a checkpoint failed");
+            return DMP_ENOMEM;
+        }
+        t->ckpt.push_back(d);
+        const hipError_t e = hipMemcpyAsync(d, src, size_t(n) * n * sizeof(double),
+                                            hipMemcpyDefault, s);
+        if (e != hipSuccess) {
+            hipPointerAttribute_t as{}, ad{};
+            const hipError_t ea = hipPointerGetAttributes(&as, src);
+            const hipError_t eb = hipPointerGetAttributes(&ad, d);
+            set_error("checkpoint copy failed: %s (src %p type %d err %d, dst %p type %d err %d, %zu bytes)",
+                      hipGetErrorString(e), (const void*)src, int(as.type), int(ea), (void*)d,
+                      int(ad.type), int(eb), size_t(n) * n * sizeof(double));
+            return DMP_EHIP;
+        }
+        return DMP_OK;
+    };
+    double* cur = P;
+    double* nxt = Pw;
+    if (!h.done) st = checkpoint(P);
+    for (int k = 0; st == DMP_OK && !h.done && k < max_iter; ++k) {
+        st = forward_iteration(x, cur, X2, nxt, true, s);
+        if (st != DMP_OK) break;
+        if (hipMemcpyAsync(&h, x.st, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            set_error("state readback failed");
+            st = DMP_EHIP;
+            break;
+        }
+        t->c.push_back(h.c);
+        t->branch.push_back(h.branch);
+        t->t1.push_back(h.t1);
+        t->t2.push_back(h.t2);
+        t->clamped.push_back(h.clamped);
+        std::swap(cur, nxt);
+        if (!h.done && (k + 1) % stride == 0) st = checkpoint(cur);
+    }
+    if (st != DMP_OK) {
+        dmp_tape_free(t);
+        return st;
+    }
+    t->K = int(t->c.size());
+    if (cur != P) {
+        if (hipMemcpyAsync(P, cur, size_t(n) * n * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            set_error("copy of the result failed");
+            dmp_tape_free(t);
+            return DMP_EHIP;
+        }
+    }
+    if (E) *E = h.E;
+    if (info) {
+        info->iters = h.iters;
+        info->stop_reason = h.stop_reason;
+        info->slices = slices;
+        info->kind = int(kind);
+        info->E = h.E;
+        info->last_dE = h.dE;
+        info->trace = h.trace_p;
+        info->idem = h.t1;
+        info->h_min = h.h_min;
+        info->h_max = h.h_max;
+        info->mu = h.mu;
+        info->lambda = h.lambda;
+    }
+    *tape = t;
+    return h.stop_reason == DMP_STOP_CONVERGED ? DMP_OK : DMP_NOT_CONVERGED;
+}
+
+static size_t carve_bwd(Carver& c, const dmp_tape* t, OzCtx* x, double** bufs, double** segP,
+                        double** segX, int2** pairs) {
+    const int n = t->n;
+    const size_t nn = size_t(n) * n;
+    OzCtx tmp;
+    carve_ctx(c, x ? *x : tmp, n, t->S, t->kind);
+    for (int i = 0; i < 5; ++i) {
+        double* p = c.take<double>(nn);
+        if (bufs) bufs[i] = p;
+    }
+    for (int i = 0; i <= t->stride; ++i) {
+        double* p = c.take<double>(nn);
+        if (segP) segP[i] = p;
+    }
+    for (int i = 0; i < t->stride; ++i) {
+        double* p = c.take<double>(nn);
+        if (segX) segX[i] = p;
+    }
+    const int t32 = (n + 31) / 32;
+    int2* pr = c.take<int2>(size_t(t32) * (t32 + 1) / 2);
+    if (pairs) *pairs = pr;
+    return c.used();
+}
+
+size_t dmp_purify_bwd_workspace_bytes(const dmp_tape* t) {
+    if (!t) return 0;
+    Carver c(nullptr);
+    return carve_bwd(c, t, nullptr, nullptr, nullptr, nullptr, nullptr);
+}
+
+int dmp_purify_bwd(const dmp_tape* t, const double* Pbar, double* Hbar, void* ws, size_t ws_bytes,
+                   void* stream) {
+    clear_error();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!t || !Pbar || !Hbar) {
+        set_error("null argument");
+        return DMP_EINVAL;
+    }
+    const size_t need = dmp_purify_bwd_workspace_bytes(t);
+    if (!ws || ws_bytes < need) {
+        set_error("workspace of %zu bytes required", need);
+        return DMP_ENOMEM;
+    }
+    const int n = t->n;
+    Carver c(ws);
+    OzCtx x;
+    double* b[5];
+    std::vector<double*> segP(t->stride + 1), segX(t->stride);
+    int2* pairs = nullptr;
+    carve_bwd(c, t, &x, b, segP.data(), segX.data(), &pairs);
+    DMP_CHECK(bind_ctx(x, t->H, t->nocc, segP[0], s));
+    double *Y = b[0], *Yn = b[1], *M = b[2], *MP = b[3], *PM = b[4];
+    std::vector<int2> hp = tile_pairs32(n);
+    DMP_CHECK_HIP(hipMemcpyAsync(pairs, hp.data(), hp.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    k_sym<<<unsigned(hp.size()), 256, 0, s>>>(Pbar, Y, n, pairs);
+    DMP_CHECK_HIP(hipGetLastError());
+
+    DevState fresh = t->init;
+    fresh.done = 0;
+    fresh.iters = 0;
+    const int K = t->K;
+    const int nseg = (K + t->stride - 1) / t->stride;
+    for (int seg = nseg - 1; seg >= 0; --seg) {
+        const int start = seg * t->stride, end = std::min(start + t->stride, K);
+        DMP_CHECK_HIP(hipMemcpyAsync(segP[0], t->ckpt[seg], size_t(n) * n * sizeof(double),
+                                     hipMemcpyDeviceToDevice, s));
+        DMP_CHECK_HIP(hipMemcpyAsync(x.st, &fresh, sizeof(fresh), hipMemcpyHostToDevice, s));
+        for (int j = start; j < end; ++j)
+            DMP_CHECK(forward_iteration(x, segP[j - start], segX[j - start], segP[j - start + 1], false, s));
+        for (int j = end - 1; j >= start; --j) {
+            const double* P = segP[j - start];
+            const double* X2 = segX[j - start];
+            // M = Y P, MP = M P, PM = P M
+            DMP_CHECK(launch_split(split_of(x, Y, false, x.ma, x.ea, x.pa, -1), x.S, x.kind, nullptr, s));
+            DMP_CHECK(launch_split(split_of(x, P, false, x.mb, x.eb, x.pb, -1), x.S, x.kind, nullptr, s));
+            DMP_CHECK(gemm_store(x, x.pa, x.ea, x.pb, x.eb, M, s));
+            DMP_CHECK(launch_split(split_of(x, M, false, x.ma, x.ea, x.pa, -1), x.S, x.kind, nullptr, s));
+            DMP_CHECK(gemm_store(x, x.pa, x.ea, x.pb, x.eb, MP, s));
+            DMP_CHECK(launch_split(split_of(x, M, true, x.ma, x.ea, x.pa, -1), x.S, x.kind, nullptr, s));
+            DMP_CHECK(gemm_store(x, x.pb, x.eb, x.pa, x.ea, PM, s));
+            const double cc = t->c[j];
+            const int br = t->branch[j];
+            double a, bb, g;
+            if (br) {
+                a = 0.0;
+                bb = (1.0 + cc) / cc;
+                g = -1.0 / cc;
+            } else {
+                a = (1.0 - 2.0 * cc) / (1.0 - cc);
+                bb = (1.0 + cc) / (1.0 - cc);
+                g = -1.0 / (1.0 - cc);
+            }
+            k_adj_dots<<<kDotBlocks, 256, 0, s>>>(Y, P, X2, MP, n, x.dots);
+            k_adj_cbar<<<1, 256, 0, s>>>(x.dots, cc, br, t->clamped[j], x.scal);
+            k_adj_combine<<<unsigned(hp.size()), 256, 0, s>>>(Y, M, MP, PM, P, X2, Yn, n, a, bb, g,
+                                                               t->t1[j], t->t2[j], x.scal, pairs);
+            DMP_CHECK_HIP(hipGetLastError());
+            std::swap(Y, Yn);
+        }
+    }
+    const DevState& i0 = t->init;
+    k_adj_dots0<<<kDotBlocks, 256, 0, s>>>(Y, t->H, n, x.dots);
+    k_adj_scal0<<<1, 256, 0, s>>>(x.dots, x.scal);
+    k_adj_initial<<<1024, 256, 0, s>>>(Y, t->H, Hbar, n, i0.lambda, i0.mu, i0.theta, i0.h_min, i0.h_max,
+                                       i0.which, i0.row_hmax, i0.row_hmin, x.scal);
+    DMP_CHECK_HIP(hipGetLastError());
+    DMP_CHECK_HIP(hipStreamSynchronize(s));
+    return DMP_OK;
+}
 
 }  // extern "C"

@@ -99,7 +99,10 @@ struct DevState {
     double E, E_prev, dE, dE_prev, trace_p, tol;
     int iters, done, stop_reason, branch;
     int max_iter, nonfinite, n, nocc;
-    int clamped, pad_[3];
+    int clamped;          // c_k clamped (or t1 == 0): no dependence of c on P
+    int row_hmax;         // first row attaining h_max (Gershgorin)
+    int row_hmin;         // first row attaining h_min
+    int which;            // 0: lam = theta / (h_max - mu), 1: (1 - theta) / (mu - h_min)
 };
 
 // One operand to split (single launch: passed by value; grouped launch: an
@@ -118,6 +121,20 @@ struct SplitDesc {
     int ub_digits;      // first k_digits unit of this matrix (grouped)
     int state_index;    // -1: no state
     int pad_;
+};
+
+// Per-matrix arguments of the small purification kernels.
+struct PurDesc {
+    const double* H;
+    double* Pb[2];          // ping-pong iterates; Pb[0] is the caller's P
+    double* X2;             // square (Ozaki) / X2 (native)
+    double* X3;             // native only: X2 P
+    double* rows;           // [3 n]: Gershgorin low, high, diagonal per row
+    int* rowbad;            // [n]: non-finite flag per row
+    double* e0;             // [kE0Blocks] partial energies of P0
+    double* partials;       // [(tile or block) count][kPartials]
+    int n, nocc;
+    int part_begin, part_end;   // partial range of this matrix
 };
 
 // Epilogue modes of the slice GEMM.

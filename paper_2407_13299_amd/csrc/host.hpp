@@ -68,4 +68,11 @@ int purify_many(int count, const double* const* H, const int* n, const int* nocc
                 dmp_info* info, void* ws, size_t ws_bytes, hipStream_t s, size_t* need_out);
 int64_t chunks_of(int k, dmp_kind kind);
 
+// Small purification kernels (purify.hip), one block / matrix per entry of pd.
+int launch_purify_init(const PurDesc* pd, DevState* st, int count, int max_n, double tol,
+                       int max_iter, hipStream_t s);
+int launch_finalize_coef(const PurDesc* pd, DevState* st, int count, hipStream_t s);
+int launch_finalize_iter(const PurDesc* pd, DevState* st, int count, hipStream_t s);
+int e0_blocks();
+
 }  // namespace dmp

@@ -41,20 +41,6 @@ struct PendingTimer {
 };
 constexpr double kStagnationWindow = 1e-2;
 
-// Per-matrix arguments of the small purification kernels.
-struct PurDesc {
-    const double* H;
-    double* Pb[2];          // ping-pong iterates; Pb[0] is the caller's P
-    double* X2;             // square (Ozaki) / X2 (native)
-    double* X3;             // native only: X2 P
-    double* rows;           // [3 n]: Gershgorin low, high, diagonal per row
-    int* rowbad;            // [n]: non-finite flag per row
-    double* e0;             // [kE0Blocks] partial energies of P0
-    double* partials;       // [(tile or block) count][kPartials]
-    int n, nocc;
-    int part_begin, part_end;   // partial range of this matrix
-};
-
 __device__ inline double wsum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
@@ -133,6 +119,14 @@ __global__ __launch_bounds__(256) void k_finalize_init(const PurDesc* pd, DevSta
     hi = block_max(hi, sh);
     tr = block_sum(tr, sh);
     const double anybad = block_max(double(bad), sh);
+    // first rows attaining the bounds (the subgradient rows of the adjoint)
+    double ilo = 1e300, ihi = 1e300;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        if (d.rows[i] == lo) ilo = fmin(ilo, double(i));
+        if (d.rows[n + i] == hi) ihi = fmin(ihi, double(i));
+    }
+    ilo = block_min(ilo, sh);
+    ihi = block_min(ihi, sh);
     if (threadIdx.x == 0) {
         s = DevState{};
         s.n = n;
@@ -141,6 +135,8 @@ __global__ __launch_bounds__(256) void k_finalize_init(const PurDesc* pd, DevSta
         s.max_iter = max_iter;
         s.h_min = lo;
         s.h_max = hi;
+        s.row_hmin = ilo < 1e300 ? int(ilo) : 0;
+        s.row_hmax = ihi < 1e300 ? int(ihi) : 0;
         s.trace_h = tr;
         s.mu = tr / n;
         s.theta = double(d.nocc) / n;
@@ -149,6 +145,7 @@ __global__ __launch_bounds__(256) void k_finalize_init(const PurDesc* pd, DevSta
             const double a = (hi - s.mu) > 0.0 ? s.theta / (hi - s.mu) : 0.0;
             const double b = (s.mu - lo) > 0.0 ? (1.0 - s.theta) / (s.mu - lo) : 0.0;
             lam = fmin(a, b);
+            s.which = a <= b ? 0 : 1;
         } else {
             s.done = 1;   // P = 0 or I exactly, no iterations
             s.stop_reason = DMP_STOP_CONVERGED;
@@ -338,6 +335,33 @@ __global__ __launch_bounds__(256) void k_native_update(const PurDesc* pd, const 
         d.partials[int64_t(blockIdx.x) * kPartials + 1] = st;
     }
 }
+
+// ---------------------------------------------------------------------------
+// Host wrappers of the small kernels (also used by the adjoint).
+
+int launch_purify_init(const PurDesc* pd, DevState* st, int count, int max_n, double tol,
+                       int max_iter, hipStream_t s) {
+    k_gershgorin<<<dim3((max_n + 3) / 4, count), 256, 0, s>>>(pd);
+    k_finalize_init<<<count, 256, 0, s>>>(pd, st, tol, max_iter);
+    k_init_p0<<<dim3(kE0Blocks, count), 256, 0, s>>>(pd, st);
+    k_finalize_e0<<<count, 256, 0, s>>>(pd, st);
+    DMP_CHECK_HIP(hipGetLastError());
+    return DMP_OK;
+}
+
+int launch_finalize_coef(const PurDesc* pd, DevState* st, int count, hipStream_t s) {
+    k_finalize_coef<<<count, 256, 0, s>>>(pd, st);
+    DMP_CHECK_HIP(hipGetLastError());
+    return DMP_OK;
+}
+
+int launch_finalize_iter(const PurDesc* pd, DevState* st, int count, hipStream_t s) {
+    k_finalize_iter<<<count, 256, 0, s>>>(pd, st);
+    DMP_CHECK_HIP(hipGetLastError());
+    return DMP_OK;
+}
+
+int e0_blocks() { return kE0Blocks; }
 
 // ---------------------------------------------------------------------------
 // Host driver.
@@ -552,12 +576,7 @@ int upload_group(GroupPlan& g, const double* const* H, double* const* P, const i
 }
 
 int launch_init(GroupPlan& g, double tol, int max_iter, hipStream_t s) {
-    k_gershgorin<<<dim3((g.max_n + 3) / 4, g.count), 256, 0, s>>>(g.pd);
-    k_finalize_init<<<g.count, 256, 0, s>>>(g.pd, g.st, tol, max_iter);
-    k_init_p0<<<dim3(kE0Blocks, g.count), 256, 0, s>>>(g.pd, g.st);
-    k_finalize_e0<<<g.count, 256, 0, s>>>(g.pd, g.st);
-    DMP_CHECK_HIP(hipGetLastError());
-    return DMP_OK;
+    return launch_purify_init(g.pd, g.st, g.count, g.max_n, tol, max_iter, s);
 }
 
 double gemm_ops(const GroupPlan& g, const int* n) {
