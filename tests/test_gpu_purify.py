@@ -66,7 +66,8 @@ def test_native_matches_ozaki_iterations_2048():
 
 
 def test_slice_sweep_error_decreases():
-    """Error against slice count on the n = 2048 tight-binding workload."""
+    """Error against slice count on the n = 2048 tight-binding workload,
+    INT8 and FP16 matrix cores (run with -s to see the table)."""
     w = workload("tb_2048")
     h, nocc = w["H"], w["nocc"]
     p_ref, e_ref, _, _ = projector.eigh_projector(h, nocc)
@@ -78,7 +79,9 @@ def test_slice_sweep_error_decreases():
         for s in range(4, 8):
             assert errs[(kind, s + 1)][0] < errs[(kind, s)][0]
         assert errs[(kind, 7)][0] < TOL_P and errs[(kind, 8)][0] < TOL_P
-    print("slice sweep", errs)
+    print("slice sweep (kind, S): (max|dP|, |dE|, stop)")
+    for key in sorted(errs):
+        print(f"  {key[0]:5s} S={key[1]}: max|dP|={errs[key][0]:.2e} |dE|={errs[key][1]:.2e} {errs[key][2]}")
 
 
 @pytest.mark.parametrize("n", [2, 3, 63, 65, 130, 200])
