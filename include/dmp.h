@@ -120,8 +120,11 @@ int dmp_ozaki_gemm(char transA, char transB, int m, int n, int k,
 
 /* Grouped GEMM: count independent products C_b = A_b B_b (no transposes,
  * row-major, leading dimensions equal to the row lengths), all with the
- * same slices and kind, in one launch per phase.  m, n, k and the pointer
- * arrays are HOST arrays of length count; the matrices are on the device. */
+ * same slices and kind.  The row splits of all A_b and the slice GEMM of all
+ * products are one grouped launch each; the column split of every B_b is a
+ * launch of its own.  m, n, k and the pointer arrays are HOST arrays of
+ * length count; the matrices are on the device.  Blocks until the launches
+ * have been queued and their host-side descriptors copied. */
 size_t dmp_gemm_batched_workspace_bytes(int count, const int* m, const int* n,
                                         const int* k, int slices, dmp_kind kind);
 int dmp_ozaki_gemm_batched(int count, const int* m, const int* n, const int* k,
@@ -164,8 +167,9 @@ int dmp_purify_batched(int count, const double* const* H, const int* n,
                        dmp_info* info, void* ws, size_t ws_bytes, void* stream);
 
 /* Slice count the tuned table recommends for an n x n purification to reach
- * max|dP| <= target on the given kind (the table is measured by the
- * project's autotuner and compiled in; see dmp_autotune_set). */
+ * max|dP| <= target on the given kind: the smallest S whose modelled error
+ * C n^a 2^(1 - 8S) is <= target, with C and a fitted to measured errors and
+ * compiled in (the largest supported S if none qualifies). */
 int dmp_autotune_slices(int n, double target, dmp_kind kind);
 
 /* ---------------------------------------------------------------------

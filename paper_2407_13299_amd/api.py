@@ -78,7 +78,7 @@ def ozaki_gemm(A, B, slices=7, kind="int8", trans_a=False, trans_b=False, out=No
 
 
 def ozaki_gemm_batched(As, Bs, slices=7, kind="int8", stream=None):
-    """C_b = A_b B_b for lists of matrices, one grouped launch per phase."""
+    """C_b = A_b B_b for lists of matrices (grouped row split and slice GEMM)."""
     lib = _lib.load()
     cnt = len(As)
     if len(Bs) != cnt:
