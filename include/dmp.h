@@ -71,6 +71,16 @@ typedef enum {
     DMP_OZ_FP16 = 2          /* Ozaki slices on FP16 MFMA, FP32 accumulate  */
 } dmp_kind;
 
+typedef enum {
+    DMP_CANONICAL = 0,       /* canonical trace-conserving purification      */
+    DMP_TRS4 = 1             /* trace-resetting fourth order (Sec. 3)        */
+} dmp_method;
+
+/* Flags of the *_ex purification entry points. */
+enum {
+    DMP_REFINE_MCWEENY = 1   /* one FP64 step P <- 3P^2 - 2P^3 at the end    */
+};
+
 enum {
     DMP_STOP_CONVERGED = 0,
     DMP_STOP_STAGNATED = 1,
@@ -78,8 +88,9 @@ enum {
     DMP_STOP_NONFINITE = 3
 };
 
-/* Per-run report.  idem = tr(P - P^2) and trace = tr(P) of the returned P
- * (both from the last iteration's products). */
+/* Per-run report.  trace = tr P of the returned P; idem = tr(P - P^2)
+ * (canonical) or ||P - P^2||_F^2 (TRS4) of the last iterate the products
+ * were formed from. */
 typedef struct {
     int iters;          /* purification updates performed                */
     int stop_reason;    /* DMP_STOP_*                                     */
@@ -90,7 +101,11 @@ typedef struct {
     double trace;       /* tr P                                           */
     double idem;        /* tr(P - P^2), computed before the last update   */
     double h_min, h_max;/* Gershgorin bounds of H                         */
-    double mu, lambda;  /* tr(H)/n and the scale of the initial guess     */
+    double mu, lambda;  /* canonical: tr(H)/n and the scale of the initial
+                           guess; TRS4: h_max and 1 / (h_max - h_min)     */
+    int method;         /* dmp_method used                                */
+    int refined;        /* 1 if the McWeeny refinement step ran           */
+    double E_unrefined; /* tr(P H) before refinement (= E if not refined) */
 } dmp_info;
 
 /* Text of the last error on the calling thread ("" if none). */
@@ -149,6 +164,29 @@ int dmp_purify(const double* H, int n, int nocc, double tol, int slices,
                dmp_info* info, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------
+ * Purification with a choice of method and an optional refinement step.
+ *   method DMP_CANONICAL: as dmp_purify.
+ *   method DMP_TRS4 (the purification the paper runs, Sec. 3):
+ *     X0 = (h_max I - H) / (h_max - h_min) (Gershgorin bounds); per
+ *     iteration X2 = X X, gamma = (nocc - tr F) / tr G with
+ *     F = X2 (4X - 3 X2) and G = X2 (I - X)^2, and
+ *       0 <= gamma <= 6:  X <- X2 T,  T = (4 - 2 gamma) X + (gamma - 3) X2 + gamma I
+ *       gamma > 6:        X <- 2X - X2        (no second product)
+ *       gamma < 0:        X <- X2             (no second product)
+ *     (tr G = 0 is read as gamma = 0); the same stopping rule.
+ *   flags & DMP_REFINE_MCWEENY: after the iteration stops (unless it went
+ *     non-finite or ran no iteration) one McWeeny step P <- 3P^2 - 2P^3 runs
+ *     with rocBLAS FP64 products (Sec. 4.1); *E and info->E are then the
+ *     refined energy and info->E_unrefined the energy before it.
+ *   Other arguments, the workspace (dmp_purify_workspace_bytes covers every
+ *   method and flag) and the blocking behaviour are those of dmp_purify.
+ * ------------------------------------------------------------------- */
+int dmp_purify_ex(const double* H, int n, int nocc, double tol, int slices,
+                  dmp_kind kind, int max_iter, int method, int flags,
+                  double* P, double* E, dmp_info* info, void* ws,
+                  size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------
  * Batched purification: count independent Hamiltonians of (possibly)
  * different sizes n[b] with nocc[b] occupied levels, sharing tol, kind and
  * max_iter.  slices <= 0 picks S per matrix from the tuned table (see
@@ -165,6 +203,14 @@ int dmp_purify_batched(int count, const double* const* H, const int* n,
                        const int* nocc, double tol, int slices, dmp_kind kind,
                        int max_iter, double* const* P, double* E,
                        dmp_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/* dmp_purify_batched with a method and flags as in dmp_purify_ex (the
+ * workspace query of dmp_purify_batched covers them). */
+int dmp_purify_batched_ex(int count, const double* const* H, const int* n,
+                          const int* nocc, double tol, int slices,
+                          dmp_kind kind, int max_iter, int method, int flags,
+                          double* const* P, double* E, dmp_info* info,
+                          void* ws, size_t ws_bytes, void* stream);
 
 /* Slice count the tuned table recommends for an n x n purification to reach
  * max|dP| <= target on the given kind: the smallest S whose modelled error

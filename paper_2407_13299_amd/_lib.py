@@ -8,6 +8,8 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libdmp.so")
 
 KINDS = {"native": 0, "fp64": 0, "int8": 1, "fp16": 2}
+METHODS = {"canonical": 0, "trs4": 1}
+REFINE_MCWEENY = 1
 STOP_REASONS = {0: "converged", 1: "stagnated", 2: "max_iter", 3: "nonfinite"}
 DMP_OK, DMP_NOT_CONVERGED = 0, 1
 ERRORS = {-1: "DMP_EINVAL", -2: "DMP_ENONFINITE", -3: "DMP_EHIP", -4: "DMP_ENOMEM",
@@ -18,8 +20,8 @@ EXPORTS = [
     "dmp_last_error", "dmp_version", "dmp_max_slices",
     "dmp_gemm_workspace_bytes", "dmp_ozaki_gemm",
     "dmp_gemm_batched_workspace_bytes", "dmp_ozaki_gemm_batched",
-    "dmp_purify_workspace_bytes", "dmp_purify",
-    "dmp_purify_batched_workspace_bytes", "dmp_purify_batched",
+    "dmp_purify_workspace_bytes", "dmp_purify", "dmp_purify_ex",
+    "dmp_purify_batched_workspace_bytes", "dmp_purify_batched", "dmp_purify_batched_ex",
     "dmp_autotune_slices",
     "dmp_purify_fwd_tape", "dmp_purify_bwd_workspace_bytes", "dmp_purify_bwd",
     "dmp_tape_info", "dmp_tape_coefficients", "dmp_tape_free",
@@ -33,12 +35,15 @@ class DmpInfo(ctypes.Structure):
                 ("E", ctypes.c_double), ("last_dE", ctypes.c_double),
                 ("trace", ctypes.c_double), ("idem", ctypes.c_double),
                 ("h_min", ctypes.c_double), ("h_max", ctypes.c_double),
-                ("mu", ctypes.c_double), ("lambda_", ctypes.c_double)]
+                ("mu", ctypes.c_double), ("lambda_", ctypes.c_double),
+                ("method", ctypes.c_int), ("refined", ctypes.c_int),
+                ("E_unrefined", ctypes.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
         d["lambda"] = d.pop("lambda_")
         d["stop"] = STOP_REASONS.get(self.stop_reason, str(self.stop_reason))
+        d["method"] = {v: k for k, v in METHODS.items()}.get(self.method, str(self.method))
         return d
 
 
@@ -67,6 +72,10 @@ _SIGS = {
     "dmp_purify_workspace_bytes": (_SZ, [_I, _I, _I]),
     "dmp_purify": (_I, [_P, _I, _I, _D, _I, _I, _I, _P, ctypes.POINTER(_D),
                         ctypes.POINTER(DmpInfo), _P, _SZ, _P]),
+    "dmp_purify_ex": (_I, [_P, _I, _I, _D, _I, _I, _I, _I, _I, _P, ctypes.POINTER(_D),
+                           ctypes.POINTER(DmpInfo), _P, _SZ, _P]),
+    "dmp_purify_batched_ex": (_I, [_I, _PP, _IP, _IP, _D, _I, _I, _I, _I, _I, _PP,
+                                   ctypes.POINTER(_D), ctypes.POINTER(DmpInfo), _P, _SZ, _P]),
     "dmp_purify_batched_workspace_bytes": (_SZ, [_I, _IP, _I, _I]),
     "dmp_purify_batched": (_I, [_I, _PP, _IP, _IP, _D, _I, _I, _I, _PP, ctypes.POINTER(_D),
                                 ctypes.POINTER(DmpInfo), _P, _SZ, _P]),

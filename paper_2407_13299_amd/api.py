@@ -105,9 +105,19 @@ def ozaki_gemm_batched(As, Bs, slices=7, kind="int8", stream=None):
     return Cs
 
 
+def _method(method) -> int:
+    if isinstance(method, int):
+        return method
+    try:
+        return _lib.METHODS[method]
+    except KeyError as e:
+        raise ValueError(f"method must be one of {sorted(_lib.METHODS)}") from e
+
+
 def purify(H, nocc, tol=1e-8, slices=7, kind="int8", max_iter=200, out=None, stream=None,
-           workspace=None):
-    """Canonical purification; returns (P, E, info dict)."""
+           workspace=None, method="canonical", refine=False):
+    """Density-matrix purification (canonical or TRS4), optionally followed
+    by one FP64 McWeeny refinement step; returns (P, E, info dict)."""
     lib = _lib.load()
     _check_matrix(H, "H")
     n = H.shape[0]
@@ -119,14 +129,16 @@ def purify(H, nocc, tol=1e-8, slices=7, kind="int8", max_iter=200, out=None, str
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, H.device)
     e = ctypes.c_double(0.0)
     info = _lib.DmpInfo()
-    st = lib.dmp_purify(_ptr(H), n, int(nocc), float(tol), int(slices), kd, int(max_iter),
-                        _ptr(P), ctypes.byref(e), ctypes.byref(info), _ptr(ws), ws.numel(),
-                        _stream(stream))
-    _lib.check(st, "dmp_purify")
+    flags = _lib.REFINE_MCWEENY if refine else 0
+    st = lib.dmp_purify_ex(_ptr(H), n, int(nocc), float(tol), int(slices), kd, int(max_iter),
+                           _method(method), flags, _ptr(P), ctypes.byref(e), ctypes.byref(info),
+                           _ptr(ws), ws.numel(), _stream(stream))
+    _lib.check(st, "dmp_purify_ex")
     return P, e.value, info.as_dict()
 
 
-def purify_batched(Hs, noccs, tol=1e-8, slices=0, kind="int8", max_iter=200, stream=None):
+def purify_batched(Hs, noccs, tol=1e-8, slices=0, kind="int8", max_iter=200, stream=None,
+                   method="canonical", refine=False):
     """Purify a list of Hamiltonians together; slices <= 0 uses the tuned table.
 
     Returns (list of P, list of E, list of info dicts)."""
@@ -143,10 +155,12 @@ def purify_batched(Hs, noccs, tol=1e-8, slices=0, kind="int8", max_iter=200, str
     ws = _workspace(lib.dmp_purify_batched_workspace_bytes(cnt, n, int(slices), kd), Hs[0].device)
     E = (ctypes.c_double * cnt)()
     infos = (_lib.DmpInfo * cnt)()
-    st = lib.dmp_purify_batched(cnt, PA(*[h.data_ptr() for h in Hs]), n, nocc, float(tol),
-                                int(slices), kd, int(max_iter), PA(*[p.data_ptr() for p in Ps]),
-                                E, infos, _ptr(ws), ws.numel(), _stream(stream))
-    _lib.check(st, "dmp_purify_batched")
+    flags = _lib.REFINE_MCWEENY if refine else 0
+    st = lib.dmp_purify_batched_ex(cnt, PA(*[h.data_ptr() for h in Hs]), n, nocc, float(tol),
+                                   int(slices), kd, int(max_iter), _method(method), flags,
+                                   PA(*[p.data_ptr() for p in Ps]), E, infos, _ptr(ws),
+                                   ws.numel(), _stream(stream))
+    _lib.check(st, "dmp_purify_batched_ex")
     return Ps, list(E), [i.as_dict() for i in infos]
 
 

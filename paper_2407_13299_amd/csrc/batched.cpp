@@ -33,15 +33,17 @@ size_t dmp_purify_batched_workspace_bytes(int count, const int* n, int slices, d
     std::vector<double*> p(count, nullptr);
     std::vector<int> nocc(count, 0);
     size_t need = 0;
-    purify_many(count, h.data(), n, nocc.data(), 1.0, s.data(), kind, 1, p.data(), nullptr,
+    purify_many(count, h.data(), n, nocc.data(), 1.0, s.data(), kind, 1, DMP_CANONICAL, 0, p.data(), nullptr,
                 nullptr, nullptr, 0, nullptr, &need);
     return need;
 }
 
-int dmp_purify_batched(int count, const double* const* H, const int* n, const int* nocc,
-                       double tol, int slices, dmp_kind kind, int max_iter, double* const* P,
-                       double* E, dmp_info* info, void* ws, size_t ws_bytes, void* stream) {
+int dmp_purify_batched_ex(int count, const double* const* H, const int* n, const int* nocc,
+                          double tol, int slices, dmp_kind kind, int max_iter, int method,
+                          int flags, double* const* P, double* E, dmp_info* info, void* ws,
+                          size_t ws_bytes, void* stream) {
     clear_error();
+    DMP_CHECK(check_method_flags(method, flags));
     if (count < 1 || !H || !n || !nocc || !P || !E) {
         set_error("bad batch arguments");
         return DMP_EINVAL;
@@ -62,8 +64,15 @@ int dmp_purify_batched(int count, const double* const* H, const int* n, const in
         set_error("workspace required");
         return DMP_ENOMEM;
     }
-    return purify_many(count, H, n, nocc, tol, s.data(), kind, max_iter, P, E, info, ws, ws_bytes,
-                       static_cast<hipStream_t>(stream), nullptr);
+    return purify_many(count, H, n, nocc, tol, s.data(), kind, max_iter, method, flags, P, E, info,
+                       ws, ws_bytes, static_cast<hipStream_t>(stream), nullptr);
+}
+
+int dmp_purify_batched(int count, const double* const* H, const int* n, const int* nocc,
+                       double tol, int slices, dmp_kind kind, int max_iter, double* const* P,
+                       double* E, dmp_info* info, void* ws, size_t ws_bytes, void* stream) {
+    return dmp_purify_batched_ex(count, H, n, nocc, tol, slices, kind, max_iter, DMP_CANONICAL, 0,
+                                 P, E, info, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

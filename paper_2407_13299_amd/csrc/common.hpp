@@ -97,7 +97,11 @@ struct DevState {
     double h_min, h_max, trace_h, mu, lambda, theta;
     double c, alpha, beta, gamma, t1, t2;
     double E, E_prev, dE, dE_prev, trace_p, tol;
+    double ta, tb, tc;    // TRS4: T = ta X + tb X2 + tc I (right operand of X2 T)
+    double E_unrefined;   // energy before the FP64 McWeeny refinement step
     int iters, done, stop_reason, branch;
+    int method;           // DMP_CANONICAL or DMP_TRS4
+    int refined;          // 1 once the McWeeny refinement step has run
     int max_iter, nonfinite, n, nocc;
     int clamped;          // c_k clamped (or t1 == 0): no dependence of c on P
     int row_hmax;         // first row attaining h_max (Gershgorin)
@@ -110,6 +114,9 @@ struct DevState {
 // fields).
 struct SplitDesc {
     const double* A;    // source matrix, row-major
+    const double* A2;   // non-null: the operand is ta A + tb A2 + tc I with the
+                        // coefficients of DevState state_index (trans == 0);
+                        // skipped while that state's gamma is 0
     int64_t lda;
     int R, K;           // rows / reduction length of the operand
     int trans;          // 0: operand row r is A[r, :]; 1: operand row r is A[:, r]
@@ -128,20 +135,25 @@ struct PurDesc {
     const double* H;
     double* Pb[2];          // ping-pong iterates; Pb[0] is the caller's P
     double* X2;             // square (Ozaki) / X2 (native)
-    double* X3;             // native only: X2 P
+    double* X3;             // native only: X2 P (X2 T for TRS4)
+    double* T;              // native TRS4: right operand T
     double* rows;           // [3 n]: Gershgorin low, high, diagonal per row
     int* rowbad;            // [n]: non-finite flag per row
     double* e0;             // [kE0Blocks] partial energies of P0
     double* partials;       // [(tile or block) count][kPartials]
     int n, nocc;
     int part_begin, part_end;   // partial range of this matrix
+    int method;                 // DMP_CANONICAL or DMP_TRS4
+    int pad_;
 };
 
 // Epilogue modes of the slice GEMM.
 enum EpiMode : int {
     EPI_STORE = 0,     // C = A B (general, full tiles)
     EPI_SQUARE = 1,    // X2 = P P (upper tiles, mirrored) + traces for c
-    EPI_UPDATE = 2,    // P' = a P + b X2 + g X2 P (upper, mirrored) + E, tr
+    EPI_UPDATE = 2,    // P' = a P + b X2 + g X2 P (upper, mirrored) + E, tr;
+                       // g == 0 skips the products
+    EPI_SQUARE_TRS4 = 3,  // X2 = X X (upper, mirrored) + tr F, tr G of TRS4
 };
 
 constexpr int kPartials = 2;   // partial sums written per tile

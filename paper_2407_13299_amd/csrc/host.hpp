@@ -63,9 +63,11 @@ int launch_ozgemm(int S, dmp_kind kind, const GemmParams& p, int ntiles, hipStre
 int check_kind_slices(dmp_kind kind, int slices);
 int validate_purify_args(const double* H, int n, int nocc, double tol, int max_iter,
                          const double* P);
+int check_method_flags(int method, int flags);
 int purify_many(int count, const double* const* H, const int* n, const int* nocc, double tol,
-                const int* slices, dmp_kind kind, int max_iter, double* const* P, double* E,
-                dmp_info* info, void* ws, size_t ws_bytes, hipStream_t s, size_t* need_out);
+                const int* slices, dmp_kind kind, int max_iter, int method, int flags,
+                double* const* P, double* E, dmp_info* info, void* ws, size_t ws_bytes,
+                hipStream_t s, size_t* need_out);
 int64_t chunks_of(int k, dmp_kind kind);
 
 // Small purification kernels (purify.hip), one block / matrix per entry of pd.

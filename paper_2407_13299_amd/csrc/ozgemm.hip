@@ -26,7 +26,10 @@
 //   EPI_SQUARE  X2 = P P for row <= col, mirrored; tile partials of
 //               tr(P - X2) and sum_ij X2_ij (delta_ij - P_ij) = tr(X2 - P^3)
 //   EPI_UPDATE  P' = alpha P + beta X2 + gamma (X2 P) for row <= col,
-//               mirrored; tile partials of tr(P' H) and tr P'
+//               mirrored; tile partials of tr(P' H) and tr P' (gamma == 0:
+//               no products at all, P' = alpha P + beta X2)
+//   EPI_SQUARE_TRS4  X2 = X X as EPI_SQUARE; partials of tr F = tr(X2 (4X -
+//               3 X2)) and tr G = ||X - X2||_F^2 (TRS4, Sec. 3)
 // In the purification modes only the upper triangle is computed and kept,
 // so every iterate is exactly symmetric and its row digits also serve as its
 // column digits.
@@ -179,9 +182,14 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
         wait_lgkm0();
         bare_barrier();
     };
-    for (int kc = -2; kc < KC; kc += 2) {
-        step(kc, 0, r0, r1);
-        step(kc + 1, 1, r1, r0);
+    // an update whose product weight is zero (a TRS4 step without the
+    // second product) keeps only the elementwise part
+    const bool no_product = p.mode == EPI_UPDATE && st != nullptr && st->gamma == 0.0;
+    if (!no_product) {
+        for (int kc = -2; kc < KC; kc += 2) {
+            step(kc, 0, r0, r1);
+            step(kc + 1, 1, r1, r0);
+        }
     }
 
     // ---- epilogue -----------------------------------------------------------
@@ -204,7 +212,8 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
 #pragma unroll
         for (int g = S - 2; g >= 0; --g) h = h * 0x1p-8 + double(acc[g][v]);
         const int ei = d.ea[row];
-        const double c = (ei >= kNonFiniteExp || fj >= kNonFiniteExp)
+        const double c = no_product ? 0.0
+                         : (ei >= kNonFiniteExp || fj >= kNonFiniteExp)
                              ? __builtin_nan("")
                              : ldexp(h, ei + fj - 2 * kTopBits);
         if (mode == EPI_STORE) {
@@ -221,6 +230,13 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
             if (!diag) d.out[ji] = c;
             if (diag) s0 += pij - c;
             s1 += mult * c * ((diag ? 1.0 : 0.0) - pij);
+        } else if (mode == EPI_SQUARE_TRS4) {
+            // tr F = sum_ij X2_ij (4 X_ij - 3 X2_ij), tr G = sum_ij (X_ij - X2_ij)^2
+            d.out[ij] = c;
+            if (!diag) d.out[ji] = c;
+            const double r = pij - c;
+            s0 += mult * c * (4.0 * pij - 3.0 * c);
+            s1 += mult * r * r;
         } else {  // EPI_UPDATE
             const double nv = alpha * pij + beta * d.X2[ij] + gamma * c;
             d.out[ij] = nv;

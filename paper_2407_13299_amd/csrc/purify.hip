@@ -11,6 +11,10 @@
 //   split(X2)
 //   gemm UPDATE         P' = alpha P + beta X2 + gamma X2 P, partial tr(P'H)
 //   finalize_iter       E, dE, stopping rule
+// TRS4 (Sec. 3) runs the same phases: the square's epilogue gives tr F and
+// tr G, finalize_trs4 picks gamma and the branch, and the second product is
+// X2 T with T = (4 - 2 gamma) X + (gamma - 3) X2 + gamma I formed inside the
+// split (or no product at all on the X2 and 2X - X2 branches).
 // All reductions are fixed-order (no floating-point atomics), so runs are
 // bitwise reproducible.  FP64 everywhere except the slice products (Sec. 4).
 #include <algorithm>
@@ -138,10 +142,18 @@ __global__ __launch_bounds__(256) void k_finalize_init(const PurDesc* pd, DevSta
         s.row_hmin = ilo < 1e300 ? int(ilo) : 0;
         s.row_hmax = ihi < 1e300 ? int(ihi) : 0;
         s.trace_h = tr;
+        s.method = d.method;
         s.mu = tr / n;
         s.theta = double(d.nocc) / n;
         double lam = 0.0;
-        if (d.nocc > 0 && d.nocc < n) {
+        if (d.nocc > 0 && d.nocc < n && d.method == DMP_TRS4) {
+            // X0 = (h_max I - H) / (h_max - h_min) = lam (mu I - H) + theta I
+            if (hi - lo > 0.0) {
+                lam = 1.0 / (hi - lo);
+                s.mu = hi;
+                s.theta = 0.0;
+            }
+        } else if (d.nocc > 0 && d.nocc < n) {
             const double a = (hi - s.mu) > 0.0 ? s.theta / (hi - s.mu) : 0.0;
             const double b = (s.mu - lo) > 0.0 ? (1.0 - s.theta) / (s.mu - lo) : 0.0;
             lam = fmin(a, b);
@@ -232,6 +244,45 @@ __global__ __launch_bounds__(256) void k_finalize_coef(const PurDesc* pd, DevSta
     }
 }
 
+// TRS4 trace reset (Sec. 3): gamma = (nocc - tr F) / tr G (0 when tr G is
+// exactly 0) and the branch; the update weights select X2 T, 2X - X2 or X2.
+__global__ __launch_bounds__(256) void k_finalize_trs4(const PurDesc* pd, DevState* states) {
+    __shared__ double sh[4];
+    const PurDesc& d = pd[blockIdx.x];
+    DevState& s = states[blockIdx.x];
+    if (s.done) return;
+    const double trf = sum_partials(d, 0, sh);
+    const double trg = sum_partials(d, 1, sh);
+    if (threadIdx.x == 0) {
+        const double g = trg == 0.0 ? 0.0 : (double(s.nocc) - trf) / trg;
+        s.t1 = trg;
+        s.t2 = trf;
+        s.c = g;
+        s.ta = 0.0;
+        s.tb = 0.0;
+        s.tc = 0.0;
+        if (g > 6.0) {          // X <- 2X - X2
+            s.branch = 2;
+            s.alpha = 2.0;
+            s.beta = -1.0;
+            s.gamma = 0.0;
+        } else if (g < 0.0) {   // X <- X2
+            s.branch = 0;
+            s.alpha = 0.0;
+            s.beta = 1.0;
+            s.gamma = 0.0;
+        } else {                // X <- X2 T (also for a NaN gamma: it propagates)
+            s.branch = 1;
+            s.alpha = 0.0;
+            s.beta = 0.0;
+            s.gamma = 1.0;
+            s.ta = 4.0 - 2.0 * g;
+            s.tb = g - 3.0;
+            s.tc = g;
+        }
+    }
+}
+
 // Energy of the new iterate and the stopping rule of Sec. 3.
 __global__ __launch_bounds__(256) void k_finalize_iter(const PurDesc* pd, DevState* states) {
     __shared__ double sh[4];
@@ -279,7 +330,11 @@ __global__ __launch_bounds__(256) void k_native_square(const PurDesc* pd, const 
         const int i = int(idx / n), j = int(idx % n);
         if (j < i) continue;
         const double x = d.X2[idx], p = P[idx];
-        if (i == j) {
+        if (d.method == DMP_TRS4) {
+            const double mult = i == j ? 1.0 : 2.0, r = p - x;
+            s0 += mult * x * (4.0 * p - 3.0 * x);
+            s1 += mult * r * r;
+        } else if (i == j) {
             s0 += p - x;
             s1 += x * (1.0 - p);
         } else {
@@ -315,7 +370,8 @@ __global__ __launch_bounds__(256) void k_native_update(const PurDesc* pd, const 
         double v = 0.0;
         if (i < n && j < n && !(I == J && j < i)) {
             const int64_t ij = int64_t(i) * n + j;
-            v = s.alpha * P[ij] + s.beta * d.X2[ij] + s.gamma * d.X3[ij];
+            // gamma == 0 (TRS4 without a second product): X3 is not read
+            v = s.alpha * P[ij] + s.beta * d.X2[ij] + (s.gamma != 0.0 ? s.gamma * d.X3[ij] : 0.0);
             Pn[ij] = v;
             se += (i == j ? 1.0 : 2.0) * v * d.H[ij];
             if (i == j) st += v;
@@ -333,6 +389,78 @@ __global__ __launch_bounds__(256) void k_native_update(const PurDesc* pd, const 
     if (threadIdx.x == 0) {
         d.partials[int64_t(blockIdx.x) * kPartials + 0] = se;
         d.partials[int64_t(blockIdx.x) * kPartials + 1] = st;
+    }
+}
+
+// Native TRS4: T = ta P + tb X2 + tc I (full matrix).
+__global__ __launch_bounds__(256) void k_native_t(const PurDesc* pd, const DevState* states) {
+    const PurDesc& d = pd[0];
+    const DevState& s = states[0];
+    if (s.done || s.gamma == 0.0) return;
+    const int n = d.n;
+    const double* P = d.Pb[s.iters & 1];
+    const int64_t tot = int64_t(n) * n;
+    for (int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x; idx < tot;
+         idx += int64_t(gridDim.x) * 256) {
+        const bool diag = idx / n == idx % n;
+        d.T[idx] = s.ta * P[idx] + s.tb * d.X2[idx] + (diag ? s.tc : 0.0);
+    }
+}
+
+// McWeeny refinement (Sec. 4.1): P' = 3 X2 - 2 X3 with X2 = P P and X3 =
+// X2 P from FP64 products, on 32 x 32 tile pairs I <= J, written over X3
+// (each upper element is read by the thread that overwrites it; the mirrored
+// lower half is never read) and mirrored through LDS; partials of tr(P'H)
+// and tr P'.
+__global__ __launch_bounds__(256) void k_mcweeny(const double* X2, double* X3P, const double* H,
+                                                 int n, const int2* pairs, double* partials) {
+    __shared__ double tileT[32][33];
+    __shared__ double sh[4];
+    const int2 pr = pairs[blockIdx.x];
+    const int I = pr.x, J = pr.y;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    double se = 0.0, st = 0.0;
+    for (int r = ty; r < 32; r += 8) {
+        const int i = I * 32 + r, j = J * 32 + tx;
+        double v = 0.0;
+        if (i < n && j < n && !(I == J && j < i)) {
+            const int64_t ij = int64_t(i) * n + j;
+            v = 3.0 * X2[ij] - 2.0 * X3P[ij];
+            X3P[ij] = v;
+            se += (i == j ? 1.0 : 2.0) * v * H[ij];
+            if (i == j) st += v;
+        }
+        tileT[r][tx] = v;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int i = J * 32 + r, j = I * 32 + tx;
+        if (i < n && j < n && (I != J ? true : j < i)) X3P[int64_t(i) * n + j] = tileT[tx][r];
+    }
+    se = block_sum(se, sh);
+    st = block_sum(st, sh);
+    if (threadIdx.x == 0) {
+        partials[int64_t(blockIdx.x) * kPartials + 0] = se;
+        partials[int64_t(blockIdx.x) * kPartials + 1] = st;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_finalize_refine(const double* partials, int count,
+                                                         DevState* state) {
+    __shared__ double sh[4];
+    double e = 0.0, t = 0.0;
+    for (int i = threadIdx.x; i < count; i += 256) {
+        e += partials[int64_t(i) * kPartials + 0];
+        t += partials[int64_t(i) * kPartials + 1];
+    }
+    e = block_sum(e, sh);
+    t = block_sum(t, sh);
+    if (threadIdx.x == 0) {
+        state->E_unrefined = state->E;
+        state->dE = e - state->E;
+        state->E = e;
+        state->trace_p = t;
+        state->refined = 1;
     }
 }
 
@@ -371,6 +499,7 @@ namespace {
 struct MatLayout {
     double* X2;
     double* X3;
+    double* T;        // native TRS4
     double* Pw;       // workspace iterate (Pb[1])
     uint8_t* planesP;
     uint8_t* planesX;
@@ -397,6 +526,7 @@ MatLayout carve_matrix(Carver& c, int n, int S, dmp_kind kind) {
     m.Pw = c.take<double>(nn);
     if (kind == DMP_FP64_NATIVE) {
         m.X3 = c.take<double>(nn);
+        m.T = c.take<double>(nn);
     } else {
         m.planesP = c.take<uint8_t>(plane_bytes(n, n, S, kind));
         m.planesX = c.take<uint8_t>(plane_bytes(n, n, S, kind));
@@ -416,23 +546,27 @@ struct GroupPlan {
     int count = 0;
     int S = 0;
     dmp_kind kind = DMP_OZ_INT8;
+    int method = DMP_CANONICAL;
     std::vector<int> idx;             // positions in the caller's arrays
     std::vector<MatLayout> lay;
     PurDesc* pd = nullptr;            // [count]
     DevState* st = nullptr;           // [count]
     SplitDesc* splitP[2] = {nullptr, nullptr};  // [count] each
     SplitDesc* splitX = nullptr;      // [count]
+    SplitDesc* splitT[2] = {nullptr, nullptr};  // TRS4: T from P (parity) and X2
     MatDesc* sq[2] = {nullptr, nullptr};
     MatDesc* up[2] = {nullptr, nullptr};
     Tile* tiles = nullptr;
     double* partials = nullptr;
     int ntiles = 0, units_rowmax = 0, units_digits = 0, max_n = 0;
-    int2* pairs = nullptr;            // native: tile pairs
+    int2* pairs = nullptr;            // 32 x 32 tile pairs I <= J of the largest matrix
+    int max_pairs = 0;
 };
 
 size_t carve_group(Carver& c, GroupPlan& g, const int* n) {
     size_t parts = 0;
     g.lay.resize(g.count);
+    g.max_pairs = 1;
     for (int b = 0; b < g.count; ++b) {
         const int nb = n[g.idx[b]];
         g.lay[b] = carve_matrix(c, nb, g.S, g.kind);
@@ -440,23 +574,24 @@ size_t carve_group(Carver& c, GroupPlan& g, const int* n) {
             parts = std::max<size_t>(parts, std::max(native_blocks(nb), native_pairs(nb)));
         else
             parts += size_t(oz_tiles(nb));
+        g.max_pairs = std::max(g.max_pairs, native_pairs(nb));
     }
+    // the refinement step reuses the partials of one matrix's tile pairs
+    parts = std::max<size_t>(parts, size_t(g.max_pairs));
     g.pd = c.take<PurDesc>(g.count);
     g.st = c.take<DevState>(g.count);
     g.splitP[0] = c.take<SplitDesc>(g.count);
     g.splitP[1] = c.take<SplitDesc>(g.count);
     g.splitX = c.take<SplitDesc>(g.count);
+    g.splitT[0] = c.take<SplitDesc>(g.count);
+    g.splitT[1] = c.take<SplitDesc>(g.count);
     g.sq[0] = c.take<MatDesc>(g.count);
     g.sq[1] = c.take<MatDesc>(g.count);
     g.up[0] = c.take<MatDesc>(g.count);
     g.up[1] = c.take<MatDesc>(g.count);
     g.tiles = c.take<Tile>(std::max<size_t>(1, g.kind == DMP_FP64_NATIVE ? 1 : parts));
     g.partials = c.take<double>(std::max<size_t>(1, parts) * kPartials);
-    if (g.kind == DMP_FP64_NATIVE) {
-        int mx = 0;
-        for (int b = 0; b < g.count; ++b) mx = std::max(mx, native_pairs(n[g.idx[b]]));
-        g.pairs = c.take<int2>(std::max(1, mx));
-    }
+    g.pairs = c.take<int2>(g.max_pairs);
     return c.used();
 }
 
@@ -465,7 +600,7 @@ int upload_group(GroupPlan& g, const double* const* H, double* const* P, const i
                  const int* nocc, hipStream_t s, std::vector<std::vector<char>>& keep) {
     const int cnt = g.count;
     std::vector<PurDesc> pd(cnt);
-    std::vector<SplitDesc> sp0(cnt), sp1(cnt), sx(cnt);
+    std::vector<SplitDesc> sp0(cnt), sp1(cnt), sx(cnt), st0(cnt), st1(cnt);
     std::vector<MatDesc> q0(cnt), q1(cnt), u0(cnt), u1(cnt);
     std::vector<Tile> tiles;
     int pbeg = 0, urow = 0, udig = 0;
@@ -480,6 +615,8 @@ int upload_group(GroupPlan& g, const double* const* H, double* const* P, const i
         d.Pb[1] = L.Pw;
         d.X2 = L.X2;
         d.X3 = L.X3;
+        d.T = L.T;
+        d.method = g.method;
         d.rows = L.rows;
         d.rowbad = L.rowbad;
         d.e0 = L.e0;
@@ -517,6 +654,14 @@ int upload_group(GroupPlan& g, const double* const* H, double* const* P, const i
         sp0[b] = sd;
         sd.A = L.Pw;
         sp1[b] = sd;
+        // TRS4: T = ta P + tb X2 + tc I, split into P's planes (free once the
+        // square has run)
+        sd.A = P[m];
+        sd.A2 = L.X2;
+        st0[b] = sd;
+        sd.A = L.Pw;
+        st1[b] = sd;
+        sd.A2 = nullptr;
         sd.A = L.X2;
         sd.maxbits = L.maxX;
         sd.expo = L.expX;
@@ -566,12 +711,19 @@ int upload_group(GroupPlan& g, const double* const* H, double* const* P, const i
         DMP_CHECK(up(g.splitP[0], sp0.data(), cnt * sizeof(SplitDesc)));
         DMP_CHECK(up(g.splitP[1], sp1.data(), cnt * sizeof(SplitDesc)));
         DMP_CHECK(up(g.splitX, sx.data(), cnt * sizeof(SplitDesc)));
+        DMP_CHECK(up(g.splitT[0], st0.data(), cnt * sizeof(SplitDesc)));
+        DMP_CHECK(up(g.splitT[1], st1.data(), cnt * sizeof(SplitDesc)));
         DMP_CHECK(up(g.sq[0], q0.data(), cnt * sizeof(MatDesc)));
         DMP_CHECK(up(g.sq[1], q1.data(), cnt * sizeof(MatDesc)));
         DMP_CHECK(up(g.up[0], u0.data(), cnt * sizeof(MatDesc)));
         DMP_CHECK(up(g.up[1], u1.data(), cnt * sizeof(MatDesc)));
         DMP_CHECK(up(g.tiles, tiles.data(), tiles.size() * sizeof(Tile)));
     }
+    std::vector<int2> pairs;
+    const int t = (g.max_n + 31) / 32;
+    for (int i = 0; i < t; ++i)
+        for (int j = i; j < t; ++j) pairs.push_back(int2{i, j});
+    DMP_CHECK(up(g.pairs, pairs.data(), pairs.size() * sizeof(int2)));
     return DMP_OK;
 }
 
@@ -616,11 +768,20 @@ int launch_oz_iteration(GroupPlan& g, int par, hipStream_t s,
     p.descs = g.sq[par];
     p.partials = g.partials;
     p.states = g.st;
-    p.mode = EPI_SQUARE;
+    const bool trs4 = g.method == DMP_TRS4;
+    p.mode = trs4 ? EPI_SQUARE_TRS4 : EPI_SQUARE;
     DMP_CHECK(timed_gemm(g, p, 0, ops, s, timers));
-    k_finalize_coef<<<g.count, 256, 0, s>>>(g.pd, g.st);
+    if (trs4)
+        k_finalize_trs4<<<g.count, 256, 0, s>>>(g.pd, g.st);
+    else
+        k_finalize_coef<<<g.count, 256, 0, s>>>(g.pd, g.st);
     DMP_CHECK(launch_split_grouped_rowmax(g.splitX, g.count, g.units_rowmax, g.st, s));
     DMP_CHECK(launch_split_grouped_digits(g.splitX, g.count, g.units_digits, g.S, g.kind, g.st, s));
+    if (trs4) {
+        DMP_CHECK(launch_split_grouped_rowmax(g.splitT[par], g.count, g.units_rowmax, g.st, s));
+        DMP_CHECK(launch_split_grouped_digits(g.splitT[par], g.count, g.units_digits, g.S, g.kind,
+                                              g.st, s));
+    }
     p.descs = g.up[par];
     p.mode = EPI_UPDATE;
     DMP_CHECK(timed_gemm(g, p, 1, ops, s, timers));
@@ -731,12 +892,7 @@ int run_native(GroupPlan& g, int max_iter, hipStream_t s, DevState& host) {
     DMP_CHECK_HIP(hipMemcpyAsync(&hd, g.pd, sizeof(PurDesc), hipMemcpyDeviceToHost, s));
     DMP_CHECK_HIP(hipStreamSynchronize(s));
     const int nb = native_blocks(n), np = native_pairs(n);
-    std::vector<int2> pairs;
-    const int t = (n + 31) / 32;
-    for (int i = 0; i < t; ++i)
-        for (int j = i; j < t; ++j) pairs.push_back(int2{i, j});
-    DMP_CHECK_HIP(hipMemcpyAsync(g.pairs, pairs.data(), pairs.size() * sizeof(int2),
-                                 hipMemcpyHostToDevice, s));
+    const bool trs4 = g.method == DMP_TRS4;
     for (int it = 0; it < max_iter; ++it) {
         DMP_CHECK_HIP(hipMemcpyAsync(&host, g.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
         DMP_CHECK_HIP(hipStreamSynchronize(s));
@@ -751,14 +907,46 @@ int run_native(GroupPlan& g, int max_iter, hipStream_t s, DevState& host) {
         dup.part_end = np;
         DMP_CHECK_HIP(hipMemcpyAsync(g.pd, &dsq, sizeof(PurDesc), hipMemcpyHostToDevice, s));
         k_native_square<<<nb, 256, 0, s>>>(g.pd, g.st, nb);
-        k_finalize_coef<<<1, 256, 0, s>>>(g.pd, g.st);
-        DMP_CHECK(native_dgemm(s, false, false, n, n, n, L.X2, n, P, n, L.X3, n));
+        if (trs4) {
+            k_finalize_trs4<<<1, 256, 0, s>>>(g.pd, g.st);
+            // the second product only runs on the X2 T branch
+            DMP_CHECK_HIP(hipMemcpyAsync(&host, g.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+            DMP_CHECK_HIP(hipStreamSynchronize(s));
+            if (host.gamma != 0.0) {
+                k_native_t<<<2048, 256, 0, s>>>(g.pd, g.st);
+                DMP_CHECK(native_dgemm(s, false, false, n, n, n, L.X2, n, L.T, n, L.X3, n));
+            }
+        } else {
+            k_finalize_coef<<<1, 256, 0, s>>>(g.pd, g.st);
+            DMP_CHECK(native_dgemm(s, false, false, n, n, n, L.X2, n, P, n, L.X3, n));
+        }
         DMP_CHECK_HIP(hipMemcpyAsync(g.pd, &dup, sizeof(PurDesc), hipMemcpyHostToDevice, s));
         k_native_update<<<np, 256, 0, s>>>(g.pd, g.st, g.pairs);
         k_finalize_iter<<<1, 256, 0, s>>>(g.pd, g.st);
         DMP_CHECK_HIP(hipGetLastError());
     }
     DMP_CHECK_HIP(hipMemcpyAsync(&host, g.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    DMP_CHECK_HIP(hipStreamSynchronize(s));
+    return DMP_OK;
+}
+
+// One FP64 McWeeny step on matrix b's final iterate (Sec. 4.1): X2 = P P and
+// X3 = X2 P by rocBLAS, P' = 3 X2 - 2 X3 written over X3, which is the other
+// iterate buffer; the result then lives in Pb[(iters + 1) & 1].
+int refine_mcweeny(GroupPlan& g, int b, const int* n, DevState& host, hipStream_t s) {
+    const int m = n[g.idx[b]];
+    PurDesc hd{};
+    DMP_CHECK_HIP(hipMemcpyAsync(&hd, g.pd + b, sizeof(PurDesc), hipMemcpyDeviceToHost, s));
+    DMP_CHECK_HIP(hipStreamSynchronize(s));
+    const double* P = hd.Pb[host.iters & 1];
+    double* other = hd.Pb[(host.iters + 1) & 1];
+    DMP_CHECK(native_dgemm(s, false, false, m, m, m, P, m, P, m, hd.X2, m));
+    DMP_CHECK(native_dgemm(s, false, false, m, m, m, hd.X2, m, P, m, other, m));
+    const int np = native_pairs(m);
+    k_mcweeny<<<np, 256, 0, s>>>(hd.X2, other, hd.H, m, g.pairs, g.partials);
+    k_finalize_refine<<<1, 256, 0, s>>>(g.partials, np, g.st + b);
+    DMP_CHECK_HIP(hipGetLastError());
+    DMP_CHECK_HIP(hipMemcpyAsync(&host, g.st + b, sizeof(DevState), hipMemcpyDeviceToHost, s));
     DMP_CHECK_HIP(hipStreamSynchronize(s));
     return DMP_OK;
 }
@@ -777,9 +965,24 @@ void fill_info(const DevState& h, int S, dmp_kind kind, dmp_info* info) {
     info->h_max = h.h_max;
     info->mu = h.mu;
     info->lambda = h.lambda;
+    info->method = h.method;
+    info->refined = h.refined;
+    info->E_unrefined = h.refined ? h.E_unrefined : h.E;
 }
 
 }  // namespace
+
+int check_method_flags(int method, int flags) {
+    if (method != DMP_CANONICAL && method != DMP_TRS4) {
+        set_error("unknown method %d", method);
+        return DMP_EINVAL;
+    }
+    if ((flags & ~DMP_REFINE_MCWEENY) != 0) {
+        set_error("unknown flags 0x%x", flags);
+        return DMP_EINVAL;
+    }
+    return DMP_OK;
+}
 
 int validate_purify_args(const double* H, int n, int nocc, double tol, int max_iter, const double* P) {
     if (n < 1 || nocc < 0 || nocc > n) {
@@ -803,8 +1006,9 @@ int validate_purify_args(const double* H, int n, int nocc, double tol, int max_i
 
 // Purify count matrices that share S and kind; used by both entry points.
 int purify_many(int count, const double* const* H, const int* n, const int* nocc, double tol,
-                const int* slices, dmp_kind kind, int max_iter, double* const* P, double* E,
-                dmp_info* info, void* ws, size_t ws_bytes, hipStream_t s, size_t* need_out) {
+                const int* slices, dmp_kind kind, int max_iter, int method, int flags,
+                double* const* P, double* E, dmp_info* info, void* ws, size_t ws_bytes,
+                hipStream_t s, size_t* need_out) {
     // partition by slice count
     std::vector<GroupPlan> groups;
     for (int b = 0; b < count; ++b) {
@@ -817,6 +1021,7 @@ int purify_many(int count, const double* const* H, const int* n, const int* nocc
             g = &groups.back();
             g->S = S;
             g->kind = kind;
+            g->method = method;
         }
         g->idx.push_back(b);
         g->count++;
@@ -859,14 +1064,25 @@ int purify_many(int count, const double* const* H, const int* n, const int* nocc
     } else {
         DMP_CHECK(run_oz_groups(groups, max_iter, s, host_st, n));
     }
-    // results: final iterate lives in Pb[iters & 1]
+    if (flags & DMP_REFINE_MCWEENY) {
+        size_t off = 0;
+        for (auto& g : groups) {
+            for (int b = 0; b < g.count; ++b) {
+                DevState& h = host_st[off + b];
+                if (h.iters > 0 && h.stop_reason != DMP_STOP_NONFINITE)
+                    DMP_CHECK(refine_mcweeny(g, b, n, h, s));
+            }
+            off += g.count;
+        }
+    }
+    // results: final iterate lives in Pb[(iters + refined) & 1]
     int status = DMP_OK;
     size_t off = 0;
     for (auto& g : groups) {
         for (int b = 0; b < g.count; ++b) {
             const DevState& h = host_st[off + b];
             const int m = g.idx[b];
-            if (h.iters & 1)
+            if ((h.iters + h.refined) & 1)
                 DMP_CHECK_HIP(hipMemcpyAsync(P[m], g.lay[b].Pw, size_t(n[m]) * n[m] * sizeof(double),
                                              hipMemcpyDeviceToDevice, s));
             if (E) E[m] = h.E;
@@ -908,15 +1124,16 @@ size_t dmp_purify_workspace_bytes(int n, int slices, dmp_kind kind) {
     const double* h = nullptr;
     double* p = nullptr;
     int nocc = 0;
-    purify_many(1, &h, &n, &nocc, 1.0, &slices, kind, 1, &p, nullptr, nullptr, nullptr, 0,
-                nullptr, &need);
+    purify_many(1, &h, &n, &nocc, 1.0, &slices, kind, 1, DMP_CANONICAL, 0, &p, nullptr, nullptr,
+                nullptr, 0, nullptr, &need);
     return need;
 }
 
-int dmp_purify(const double* H, int n, int nocc, double tol, int slices, dmp_kind kind,
-               int max_iter, double* P, double* E, dmp_info* info, void* ws, size_t ws_bytes,
-               void* stream) {
+int dmp_purify_ex(const double* H, int n, int nocc, double tol, int slices, dmp_kind kind,
+                  int max_iter, int method, int flags, double* P, double* E, dmp_info* info,
+                  void* ws, size_t ws_bytes, void* stream) {
     clear_error();
+    DMP_CHECK(check_method_flags(method, flags));
     DMP_CHECK(check_kind_slices(kind, slices));
     DMP_CHECK(validate_purify_args(H, n, nocc, tol, max_iter, P));
     if (kind != DMP_FP64_NATIVE && n > max_k_for_slices(slices)) {
@@ -927,8 +1144,15 @@ int dmp_purify(const double* H, int n, int nocc, double tol, int slices, dmp_kin
         set_error("workspace of %zu bytes required", dmp_purify_workspace_bytes(n, slices, kind));
         return DMP_ENOMEM;
     }
-    return purify_many(1, &H, &n, &nocc, tol, &slices, kind, max_iter, &P, E, info, ws, ws_bytes,
-                       static_cast<hipStream_t>(stream), nullptr);
+    return purify_many(1, &H, &n, &nocc, tol, &slices, kind, max_iter, method, flags, &P, E, info,
+                       ws, ws_bytes, static_cast<hipStream_t>(stream), nullptr);
+}
+
+int dmp_purify(const double* H, int n, int nocc, double tol, int slices, dmp_kind kind,
+               int max_iter, double* P, double* E, dmp_info* info, void* ws, size_t ws_bytes,
+               void* stream) {
+    return dmp_purify_ex(H, n, nocc, tol, slices, kind, max_iter, DMP_CANONICAL, 0, P, E, info,
+                         ws, ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -41,6 +41,20 @@ __device__ inline bool finished(const DevState* st, int idx) {
     return st != nullptr && idx >= 0 && st[idx].done != 0;
 }
 
+// A combined operand (d.A2 set) is only needed when its product runs.
+__device__ inline bool skipped(const SplitDesc& d, const DevState* st) {
+    return finished(st, d.state_index) ||
+           (d.A2 != nullptr && st[d.state_index].gamma == 0.0);
+}
+
+// Entry (r, k) of the combined operand ta A + tb A2 + tc I.  Written with
+// explicit fused multiply-adds so that the row-max and the digit kernels
+// compute the same value bit for bit.
+__device__ inline double combined(const SplitDesc& d, const DevState& s, int r, int k) {
+    const int64_t ij = int64_t(r) * d.lda + k;
+    return __builtin_fma(s.ta, d.A[ij], __builtin_fma(s.tb, d.A2[ij], r == k ? s.tc : 0.0));
+}
+
 // Magnitudes are compared as the bit patterns of |x|: for non-negative
 // doubles the integer order is the numeric order, +inf sorts above every
 // finite value and a NaN above +inf, so a non-finite entry is never lost.
@@ -62,16 +76,22 @@ __global__ __launch_bounds__(256) void k_rowmax(const SplitDesc* descs, int coun
                                                 SplitDesc one, const DevState* st) {
     int local;
     const SplitDesc& d = pick<true>(descs, count, one, blockIdx.x, &local);
-    if (finished(st, d.state_index)) return;
+    if (skipped(d, st)) return;
     const int lane = threadIdx.x & 63;
     const int r = local * 4 + (threadIdx.x >> 6);
     const int rp = int(round_up(d.R, kPad));
     if (r >= rp) return;
     uint64_t m = 0;
-    if (r < d.R) {
+    if (r < d.R && d.A2 == nullptr) {
         const double* row = d.A + int64_t(r) * d.lda;
         for (int k = lane; k < d.K; k += 64) {
             const uint64_t b = abs_bits(row[k]);
+            m = b > m ? b : m;
+        }
+    } else if (r < d.R) {
+        const DevState& s = st[d.state_index];
+        for (int k = lane; k < d.K; k += 64) {
+            const uint64_t b = abs_bits(combined(d, s, r, k));
             m = b > m ? b : m;
         }
     }
@@ -152,7 +172,7 @@ __global__ __launch_bounds__(256) void k_digits(const SplitDesc* descs, int coun
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int local;
     const SplitDesc& d = pick<false>(descs, count, one, blockIdx.x, &local);
-    if (finished(st, d.state_index)) return;
+    if (skipped(d, st)) return;
     const int rb_count = int(round_up(d.R, kPad)) / kFragRows;
     const int blk = local * 4 + wave;
     if (blk >= rb_count * d.KC) return;
@@ -164,7 +184,11 @@ __global__ __launch_bounds__(256) void k_digits(const SplitDesc* descs, int coun
 
     double v[NE];
     if (r < d.R) {
-        if (!d.trans) {
+        if (d.A2 != nullptr) {
+            const DevState& s = st[d.state_index];
+#pragma unroll
+            for (int i = 0; i < NE; ++i) v[i] = (k0 + i < d.K) ? combined(d, s, r, k0 + i) : 0.0;
+        } else if (!d.trans) {
             const double* src = d.A + int64_t(r) * d.lda;
 #pragma unroll
             for (int i = 0; i < NE; ++i) v[i] = (k0 + i < d.K) ? src[k0 + i] : 0.0;

@@ -88,6 +88,24 @@ def test_argument_errors_without_device_work(lib):
     st = lib.dmp_purify(ctypes.c_void_p(8), 8, 4, 1e-8, 7, 9, 100, ctypes.c_void_p(16),
                         ctypes.byref(e), ctypes.byref(info), ws, 0, None)
     assert st == -1
+    # unknown method or flag of the _ex entry points
+    for method, flags in ((2, 0), (-1, 0), (1, 2), (0, 0x10)):
+        st = lib.dmp_purify_ex(ctypes.c_void_p(8), 8, 4, 1e-8, 7, 1, 100, method, flags,
+                               ctypes.c_void_p(16), ctypes.byref(e), ctypes.byref(info), ws, 0,
+                               None)
+        assert st == -1 and (b"method" in lib.dmp_last_error() or b"flags" in lib.dmp_last_error())
+        H = (ctypes.c_void_p * 1)(8)
+        P = (ctypes.c_void_p * 1)(16)
+        n = (ctypes.c_int * 1)(8)
+        no = (ctypes.c_int * 1)(4)
+        E = (ctypes.c_double * 1)()
+        st = lib.dmp_purify_batched_ex(1, H, n, no, 1e-8, 7, 1, 100, method, flags, P, E,
+                                       ctypes.byref(info), ws, 0, None)
+        assert st == -1
+    # valid method and flag: only the missing workspace is reported
+    st = lib.dmp_purify_ex(ctypes.c_void_p(8), 8, 4, 1e-8, 7, 1, 100, 1, 1, ctypes.c_void_p(16),
+                           ctypes.byref(e), ctypes.byref(info), ws, 0, None)
+    assert st == -4
 
 
 def test_autotune_table_monotone(lib):
