@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--native-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-native", action="store_true")
+    ap.add_argument("--no-trs4", action="store_true",
+                    help="skip the TRS4 leg (the purification the paper runs)")
     ap.add_argument("--max-iter", type=int, default=200,
                     help="iteration cap (short profiled runs use a few)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -208,9 +210,20 @@ def main():
     ws = torch.empty(lib.dmp_purify_workspace_bytes(n, a.slices, kind_id), dtype=torch.uint8,
                      device="cuda")
 
-    def run(kind, slices, out, wsb):
+    def run(kind, slices, out, wsb, method="canonical"):
         return dmp.purify(H, nocc, tol=tol, slices=slices, kind=kind, out=out, workspace=wsb,
-                          max_iter=a.max_iter)
+                          max_iter=a.max_iter, method=method)
+
+    def accuracy(p, e):
+        gpath = os.path.join(ROOT, "tests", "golden", "tb8192_reference.npz")
+        if a.workload != "tb_8192" or not os.path.exists(gpath):
+            return {}
+        ref = np.load(gpath)
+        samp = p[torch.from_numpy(ref["si"]).cuda(), torch.from_numpy(ref["sj"]).cuda()].cpu().numpy()
+        rows = p[torch.from_numpy(ref["rows"]).cuda()].cpu().numpy()
+        return dict(max_dP_sampled=float(max(np.max(np.abs(samp - ref["P_samples"])),
+                                             np.max(np.abs(rows - ref["P_rows"])))),
+                    dE=float(abs(e - float(ref["E"]))))
 
     if a.calibrate_copy:
         src = torch.empty(a.calibrate_copy << 20, dtype=torch.uint8, device="cuda").fill_(1)
@@ -254,15 +267,7 @@ def main():
     value = fp64_eq / (ms_per_step / 1e3) / 1e12
 
     # accuracy against the stored oracle samples
-    acc = {}
-    gpath = os.path.join(ROOT, "tests", "golden", "tb8192_reference.npz")
-    if a.workload == "tb_8192" and os.path.exists(gpath):
-        ref = np.load(gpath)
-        samp = P[torch.from_numpy(ref["si"]).cuda(), torch.from_numpy(ref["sj"]).cuda()].cpu().numpy()
-        rows = P[torch.from_numpy(ref["rows"]).cuda()].cpu().numpy()
-        acc = dict(max_dP_sampled=float(max(np.max(np.abs(samp - ref["P_samples"])),
-                                            np.max(np.abs(rows - ref["P_rows"])))),
-                   dE=float(abs(e - float(ref["E"]))))
+    acc = accuracy(P, e)
 
     # roofline of the dominant kernel: the update GEMM (X2 P), and the square
     kernels = {}
@@ -298,6 +303,36 @@ def main():
                       max_dP_ozaki_vs_native=float(torch.max(torch.abs(P - Pn)).item()))
         del wsn, Pn
 
+    # TRS4 (Sec. 3): same driver, fewer iterations; Ozaki against native
+    trs4 = None
+    if not a.no_trs4:
+        print("# trs4 leg", file=sys.stderr, flush=True)
+        run(a.kind, a.slices, P, ws, "trs4")
+        torch.cuda.synchronize()
+        tt = []
+        for _ in range(a.steps):
+            t0 = time.perf_counter()
+            _, et, infot = run(a.kind, a.slices, P, ws, "trs4")
+            torch.cuda.synchronize()
+            tt.append(time.perf_counter() - t0)
+        ms_t = float(np.median(tt)) * 1e3
+        trs4 = dict(ms_per_purification=ms_t, iters=infot["iters"], products=infot["products"],
+                    stop=infot["stop"],
+                    tflops_fp64_equiv=infot["products"] * 2.0 * n ** 3 / (ms_t / 1e3) / 1e12,
+                    speedup_vs_canonical_ozaki=ms_per_step / ms_t, **accuracy(P, et))
+        if not a.no_native:
+            wsn = torch.empty(lib.dmp_purify_workspace_bytes(n, 0, 0), dtype=torch.uint8,
+                              device="cuda")
+            Pn = torch.empty_like(H)
+            t0 = time.perf_counter()
+            _, en, infon = run("native", 0, Pn, wsn, "trs4")
+            torch.cuda.synchronize()
+            ms_tn = (time.perf_counter() - t0) * 1e3
+            trs4.update(native_ms=ms_tn, native_iters=infon["iters"],
+                        native_products=infon["products"], speedup_vs_native=ms_tn / ms_t,
+                        max_dP_vs_native=float(torch.max(torch.abs(P - Pn)).item()))
+            del wsn, Pn
+
     cpu = None
     if not a.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -330,6 +365,7 @@ def main():
                                      "copy-calibrated)",
                      "kernels": kernels},
         "native_fp64": native,
+        "trs4": trs4,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

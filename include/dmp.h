@@ -106,6 +106,8 @@ typedef struct {
     int method;         /* dmp_method used                                */
     int refined;        /* 1 if the McWeeny refinement step ran           */
     double E_unrefined; /* tr(P H) before refinement (= E if not refined) */
+    int products;       /* n x n matrix products performed (canonical: 2 per
+                           iteration; TRS4: 1 or 2; refinement: 2)        */
 } dmp_info;
 
 /* Text of the last error on the calling thread ("" if none). */

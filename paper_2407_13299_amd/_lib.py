@@ -37,7 +37,7 @@ class DmpInfo(ctypes.Structure):
                 ("h_min", ctypes.c_double), ("h_max", ctypes.c_double),
                 ("mu", ctypes.c_double), ("lambda_", ctypes.c_double),
                 ("method", ctypes.c_int), ("refined", ctypes.c_int),
-                ("E_unrefined", ctypes.c_double)]
+                ("E_unrefined", ctypes.c_double), ("products", ctypes.c_int)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}

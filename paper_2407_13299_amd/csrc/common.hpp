@@ -102,6 +102,7 @@ struct DevState {
     int iters, done, stop_reason, branch;
     int method;           // DMP_CANONICAL or DMP_TRS4
     int refined;          // 1 once the McWeeny refinement step has run
+    int products;         // matrix products performed so far
     int max_iter, nonfinite, n, nocc;
     int clamped;          // c_k clamped (or t1 == 0): no dependence of c on P
     int row_hmax;         // first row attaining h_max (Gershgorin)

@@ -299,6 +299,7 @@ __global__ __launch_bounds__(256) void k_finalize_iter(const PurDesc* pd, DevSta
         s.E = e;
         s.trace_p = tr;
         s.iters += 1;
+        s.products += s.gamma != 0.0 ? 2 : 1;
         int stop = -1;
         if (!isfinite(e)) stop = DMP_STOP_NONFINITE;
         else if (fabs(de) < s.tol) stop = DMP_STOP_CONVERGED;
@@ -461,6 +462,7 @@ __global__ __launch_bounds__(256) void k_finalize_refine(const double* partials,
         state->E = e;
         state->trace_p = t;
         state->refined = 1;
+        state->products += 2;
     }
 }
 
@@ -968,6 +970,7 @@ void fill_info(const DevState& h, int S, dmp_kind kind, dmp_info* info) {
     info->method = h.method;
     info->refined = h.refined;
     info->E_unrefined = h.refined ? h.E_unrefined : h.E;
+    info->products = h.products;
 }
 
 }  // namespace

@@ -66,6 +66,7 @@ def test_trs4_steps_match_oracle(kind):
                                 method="trs4")
         torch.cuda.synchronize()
         assert info["iters"] == k and info["stop"] == "max_iter"
+        assert info["products"] == sum(2 if b == trs4.BRANCH_RESET else 1 for b in branches[:k])
         d = np.max(np.abs(p.cpu().numpy() - x))
         assert d < 1e-12, (k, d)
         assert abs(e - float(np.sum(x * h))) < 1e-10
@@ -146,6 +147,7 @@ def test_refinement_recovers_energy_at_low_slices():
     p1, e1, i1 = gpu_purify(h, nocc, tol=w["tol"], slices=5, kind="int8", refine=True)
     assert i1["refined"] == 1 and i0["refined"] == 0
     assert i1["E_unrefined"] == e0 and i1["iters"] == i0["iters"]
+    assert i0["products"] == 2 * i0["iters"] and i1["products"] == i0["products"] + 2
     assert abs(e0 - e_ref) > 1e-9
     assert abs(e1 - e_ref) < 1e-10
     assert abs(e1 - e_ref) < 1e-2 * abs(e0 - e_ref)
