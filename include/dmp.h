@@ -68,7 +68,12 @@ typedef enum {
 typedef enum {
     DMP_FP64_NATIVE = 0,     /* products by rocBLAS DGEMM (FP64 baseline)   */
     DMP_OZ_INT8 = 1,         /* Ozaki slices on INT8 MFMA, INT32 accumulate */
-    DMP_OZ_FP16 = 2          /* Ozaki slices on FP16 MFMA, FP32 accumulate  */
+    DMP_OZ_FP16 = 2,         /* Ozaki slices on FP16 MFMA, FP32 accumulate  */
+    DMP_MARKIDIS_FP16 = 3    /* Markidis split (Sec. 4.5): high and low FP16
+                                parts after the same row / column power-of-two
+                                scaling, 1..4 term products (``slices`` counts
+                                the terms: A0B0, +A0B1, +A1B0, +A1B1) on FP16
+                                MFMA with FP32 accumulation; not exact      */
 } dmp_kind;
 
 typedef enum {
@@ -114,7 +119,8 @@ typedef struct {
 const char* dmp_last_error(void);
 /* Library version string. */
 const char* dmp_version(void);
-/* Largest supported slice count for an Ozaki kind (0 for native). */
+/* Largest supported slice count for an Ozaki kind, term count for the
+ * Markidis kind (4), 0 for native. */
 int dmp_max_slices(dmp_kind kind);
 
 /* ---------------------------------------------------------------------

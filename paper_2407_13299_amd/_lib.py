@@ -7,7 +7,7 @@ import os
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libdmp.so")
 
-KINDS = {"native": 0, "fp64": 0, "int8": 1, "fp16": 2}
+KINDS = {"native": 0, "fp64": 0, "int8": 1, "fp16": 2, "markidis": 3}
 METHODS = {"canonical": 0, "trs4": 1}
 REFINE_MCWEENY = 1
 STOP_REASONS = {0: "converged", 1: "stagnated", 2: "max_iter", 3: "nonfinite"}

@@ -53,7 +53,9 @@ def max_slices(kind="int8") -> int:
 
 def ozaki_gemm(A, B, slices=7, kind="int8", trans_a=False, trans_b=False, out=None,
                stream=None):
-    """C = op(A) op(B) by the Ozaki scheme (or rocBLAS DGEMM for kind='native')."""
+    """C = op(A) op(B) by the Ozaki scheme (kind 'int8' / 'fp16', ``slices``
+    slices), the Markidis scheme (kind 'markidis', ``slices`` = 1..4 terms) or
+    rocBLAS DGEMM (kind 'native')."""
     lib = _lib.load()
     _check_matrix(A, "A")
     _check_matrix(B, "B")

@@ -447,7 +447,7 @@ int dmp_purify_fwd_tape(const double* H, int n, int nocc, double tol, int slices
         }
     }
     DMP_CHECK(check_kind_slices(kind, slices));
-    if (kind == DMP_FP64_NATIVE) {
+    if (kind != DMP_OZ_INT8 && kind != DMP_OZ_FP16) {
         set_error("the recorded adjoint is built for the Ozaki kinds");
         return DMP_EUNSUPPORTED;
     }

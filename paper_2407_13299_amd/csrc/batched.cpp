@@ -11,6 +11,7 @@ extern "C" {
 
 int dmp_autotune_slices(int n, double target, dmp_kind kind) {
     if (kind == DMP_FP64_NATIVE) return 0;
+    if (kind == DMP_MARKIDIS_FP16) return kMaxTerms;   // no term count reaches FP64 level
     if (n < 1 || !(target > 0.0)) return kMaxSlices;
     // error model max|dP| ~ C n^a 2^-(8S - 1), with (C, a) measured per kind
     const double c = kind == DMP_OZ_FP16 ? kTunedErrC[1] : kTunedErrC[0];
@@ -54,7 +55,7 @@ int dmp_purify_batched_ex(int count, const double* const* H, const int* n, const
         s[b] = kind == DMP_FP64_NATIVE ? 0 : (slices > 0 ? slices : dmp_autotune_slices(n[b], kTunedTarget, kind));
         if (kind != DMP_FP64_NATIVE) {
             DMP_CHECK(check_kind_slices(kind, s[b]));
-            if (n[b] > max_k_for_slices(s[b])) {
+            if (n[b] > max_k_for(s[b], kind)) {
                 set_error("matrix %d: n = %d exceeds the exact INT32 range for %d slices", b, n[b], s[b]);
                 return DMP_EINVAL;
             }

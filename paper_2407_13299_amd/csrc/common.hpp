@@ -53,17 +53,28 @@ constexpr int kDigitBits = 8;        // bits of every further digit
 // products of such a row come out NaN.
 constexpr int kNonFiniteExp = 1 << 20;
 
-inline int chunk_k(dmp_kind kind) { return kind == DMP_OZ_FP16 ? 16 : 32; }
+inline bool is_fp16_kind(dmp_kind kind) { return kind == DMP_OZ_FP16 || kind == DMP_MARKIDIS_FP16; }
+inline int chunk_k(dmp_kind kind) { return is_fp16_kind(kind) ? 16 : 32; }
+// Planes stored per operand: S digit planes for the Ozaki kinds, two (the
+// high and low FP16 parts) for the Markidis kind, whose ``slices`` argument
+// counts its terms.
+inline int planes_of(int s, dmp_kind kind) { return kind == DMP_MARKIDIS_FP16 ? 2 : s; }
+constexpr int kMaxTerms = 4;
 __host__ __device__ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 // Largest reduction length whose INT32 group sums cannot overflow:
 // (g - 1) k 2^14 < 2^31 for every group g <= S + 1.
 inline int64_t max_k_for_slices(int s) { return ((1ll << 31) - 1) / (int64_t(s) * 16384); }
+// Reduction limit of a kind: the INT32 bound above for the Ozaki kinds; the
+// Markidis kind accumulates in FP32 (inexact by design) and has none.
+inline int64_t max_k_for(int s, dmp_kind kind) {
+    return kind == DMP_MARKIDIS_FP16 ? (int64_t(1) << 30) : max_k_for_slices(s);
+}
 
 // Bytes of the digit planes of an R x K operand.
 inline size_t plane_bytes(int64_t r, int64_t k, int s, dmp_kind kind) {
-    return size_t(round_up(r, kPad)) * size_t(round_up(k, kKPad)) * size_t(s) *
-           (kind == DMP_OZ_FP16 ? 2 : 1);
+    return size_t(round_up(r, kPad)) * size_t(round_up(k, kKPad)) * size_t(planes_of(s, kind)) *
+           (is_fp16_kind(kind) ? 2 : 1);
 }
 
 // One output tile of a (possibly grouped) GEMM: rows [128 I, 128 I + 128),

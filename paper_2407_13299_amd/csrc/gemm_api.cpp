@@ -47,6 +47,7 @@ extern "C" {
 size_t dmp_gemm_workspace_bytes(int m, int n, int k, int slices, dmp_kind kind) {
     if (kind == DMP_FP64_NATIVE) return 256;
     if (m < 0 || n < 0 || k < 0 || slices < 1 || slices > kMaxSlices) return 0;
+    if (kind == DMP_MARKIDIS_FP16 && slices > kMaxTerms) return 0;
     Carver c(nullptr);
     carve_gemm(c, m, n, k, slices, kind);
     return c.used();
@@ -84,9 +85,9 @@ int dmp_ozaki_gemm(char transA, char transB, int m, int n, int k, const double* 
         return DMP_OK;
     }
     if (kind == DMP_FP64_NATIVE) return native_dgemm(s, ta, tb, m, n, k, A, lda, B, ldb, C, ldc);
-    if (k > max_k_for_slices(slices)) {
+    if (k > max_k_for(slices, kind)) {
         set_error("k = %d exceeds the exact INT32 range for %d slices (max %lld)", k, slices,
-                  (long long)max_k_for_slices(slices));
+                  (long long)max_k_for(slices, kind));
         return DMP_EINVAL;
     }
     if (m > 65535 * kTileN || n > 65535 * kTileN) {
@@ -101,7 +102,7 @@ int dmp_ozaki_gemm(char transA, char transB, int m, int n, int k, const double* 
     Carver c(ws);
     GemmLayout g = carve_gemm(c, m, n, k, slices, kind);
     const int KC = int(chunks_of(k, kind));
-    const int64_t rb_stride = int64_t(KC) * slices * kFragBytes;
+    const int64_t rb_stride = int64_t(KC) * planes_of(slices, kind) * kFragBytes;
 
     SplitDesc da{};
     da.A = A;
@@ -153,6 +154,7 @@ int dmp_ozaki_gemm(char transA, char transB, int m, int n, int k, const double* 
 size_t dmp_gemm_batched_workspace_bytes(int count, const int* m, const int* n, const int* k,
                                         int slices, dmp_kind kind) {
     if (count < 0 || slices < 1 || slices > kMaxSlices) return 0;
+    if (kind == DMP_MARKIDIS_FP16 && slices > kMaxTerms) return 0;
     Carver c(nullptr);
     size_t tiles = 0;
     for (int b = 0; b < count; ++b) {
@@ -180,7 +182,7 @@ int dmp_ozaki_gemm_batched(int count, const int* m, const int* n, const int* k,
             set_error("batch entry %d: sizes must be >= 1 and pointers non-null", b);
             return DMP_EINVAL;
         }
-        if (kind != DMP_FP64_NATIVE && k[b] > max_k_for_slices(slices)) {
+        if (kind != DMP_FP64_NATIVE && k[b] > max_k_for(slices, kind)) {
             set_error("batch entry %d: k too large for %d slices", b, slices);
             return DMP_EINVAL;
         }
@@ -244,7 +246,7 @@ int dmp_ozaki_gemm_batched(int count, const int* m, const int* n, const int* k,
         q.ea = lay[b].ea;
         q.eb = lay[b].eb;
         q.out = C[b];
-        q.a_rb_stride = int64_t(KC) * slices * kFragBytes;
+        q.a_rb_stride = int64_t(KC) * planes_of(slices, kind) * kFragBytes;
         q.b_rb_stride = q.a_rb_stride;
         q.M = m[b];
         q.N = n[b];

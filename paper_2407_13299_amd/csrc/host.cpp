@@ -113,11 +113,16 @@ int native_dgemm(hipStream_t stream, bool ta, bool tb, int m, int n, int k, cons
 }
 
 int check_kind_slices(dmp_kind kind, int slices) {
-    if (kind != DMP_OZ_INT8 && kind != DMP_OZ_FP16 && kind != DMP_FP64_NATIVE) {
+    if (kind != DMP_OZ_INT8 && kind != DMP_OZ_FP16 && kind != DMP_FP64_NATIVE &&
+        kind != DMP_MARKIDIS_FP16) {
         set_error("unknown kind %d", int(kind));
         return DMP_EINVAL;
     }
-    if (kind != DMP_FP64_NATIVE && (slices < 1 || slices > kMaxSlices)) {
+    if (kind == DMP_MARKIDIS_FP16 && (slices < 1 || slices > kMaxTerms)) {
+        set_error("terms must lie in [1, %d], got %d", kMaxTerms, slices);
+        return DMP_EINVAL;
+    }
+    if (kind != DMP_FP64_NATIVE && kind != DMP_MARKIDIS_FP16 && (slices < 1 || slices > kMaxSlices)) {
         set_error("slices must lie in [1, %d], got %d", kMaxSlices, slices);
         return DMP_EINVAL;
     }
@@ -135,6 +140,7 @@ const char* dmp_last_error(void) { return dmp::g_error; }
 const char* dmp_version(void) { return "dmp 0.1 (gfx950)"; }
 
 int dmp_max_slices(dmp_kind kind) {
+    if (kind == DMP_MARKIDIS_FP16) return dmp::kMaxTerms;
     return (kind == DMP_OZ_INT8 || kind == DMP_OZ_FP16) ? dmp::kMaxSlices : 0;
 }
 

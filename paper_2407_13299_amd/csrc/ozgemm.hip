@@ -64,7 +64,10 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-template <int S, bool FP16>
+// TERMS > 0: the Markidis product (Sec. 4.5) on the same tiles: S = 2 FP16
+// planes (high, low parts), the first TERMS of A0 B0, A0 B1, A1 B0, A1 B1
+// accumulated in one FP32 accumulator, and C = acc 2^(e_i + f_j).
+template <int S, bool FP16, int TERMS = 0>
 __global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
     constexpr int BLOCKS = 6 * S;                 // 1 KiB blocks per chunk
     constexpr int STAGE = BLOCKS * kFragBytes;
@@ -115,16 +118,34 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
         }
     };
 
+    static_assert(TERMS == 0 || (S == 2 && FP16), "Markidis: two FP16 planes");
     v16i acc[S];
 #pragma unroll
     for (int g = 0; g < S; ++g)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[g][v] = 0;
+    v16f accf;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) accf[v] = 0.0f;
 
     auto compute = [&](int buf) __attribute__((always_inline)) {
         const uint8_t* sa = &lds[buf][(wm * S) * kFragBytes + lane * 16];
         const uint8_t* sb = &lds[buf][((4 + wn) * S) * kFragBytes + lane * 16];
-        if constexpr (!FP16) {
+        if constexpr (TERMS > 0) {
+            const v8h a0 = __builtin_bit_cast(v8h, *reinterpret_cast<const v4i*>(sa));
+            const v8h b0 = __builtin_bit_cast(v8h, *reinterpret_cast<const v4i*>(sb));
+            accf = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0, b0, accf, 0, 0, 0);
+            if constexpr (TERMS >= 2) {
+                const v8h b1 = __builtin_bit_cast(v8h, *reinterpret_cast<const v4i*>(sb + kFragBytes));
+                accf = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0, b1, accf, 0, 0, 0);
+                if constexpr (TERMS >= 3) {
+                    const v8h a1 = __builtin_bit_cast(v8h, *reinterpret_cast<const v4i*>(sa + kFragBytes));
+                    accf = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1, b0, accf, 0, 0, 0);
+                    if constexpr (TERMS >= 4)
+                        accf = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1, b1, accf, 0, 0, 0);
+                }
+            }
+        } else if constexpr (!FP16) {
             v4i fb[S];
 #pragma unroll
             for (int s = 0; s < S; ++s) fb[s] = *reinterpret_cast<const v4i*>(sb + s * kFragBytes);
@@ -208,14 +229,20 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         const int row = row0 + (v >> 2) * 8 + (v & 3);
-        double h = double(acc[S - 1][v]);
+        double h;
+        if constexpr (TERMS > 0) {
+            h = double(accf[v]);
+        } else {
+            h = double(acc[S - 1][v]);
 #pragma unroll
-        for (int g = S - 2; g >= 0; --g) h = h * 0x1p-8 + double(acc[g][v]);
+            for (int g = S - 2; g >= 0; --g) h = h * 0x1p-8 + double(acc[g][v]);
+        }
         const int ei = d.ea[row];
+        constexpr int shift = TERMS > 0 ? 0 : 2 * kTopBits;
         const double c = no_product ? 0.0
                          : (ei >= kNonFiniteExp || fj >= kNonFiniteExp)
                              ? __builtin_nan("")
-                             : ldexp(h, ei + fj - 2 * kTopBits);
+                             : ldexp(h, ei + fj - shift);
         if (mode == EPI_STORE) {
             if (row < d.M && col < d.N) d.out[int64_t(row) * d.ldc + col] = c;
             continue;
@@ -279,9 +306,21 @@ static const GemmFn kGemm[kMaxSlices + 1] = {
     nullptr,     launch_s<1>, launch_s<2>, launch_s<3>,  launch_s<4>,  launch_s<5>, launch_s<6>,
     launch_s<7>, launch_s<8>, launch_s<9>, launch_s<10>, launch_s<11>, launch_s<12>};
 
+template <int T>
+static void launch_terms(const GemmParams& p, int ntiles, hipStream_t stream) {
+    k_ozgemm<2, true, T><<<ntiles, kGemmThreads, 0, stream>>>(p);
+}
+
+using TermsFn = void (*)(const GemmParams&, int, hipStream_t);
+static const TermsFn kTerms[kMaxTerms + 1] = {nullptr, launch_terms<1>, launch_terms<2>,
+                                              launch_terms<3>, launch_terms<4>};
+
 int launch_ozgemm(int S, dmp_kind kind, const GemmParams& p, int ntiles, hipStream_t stream) {
     if (ntiles <= 0) return DMP_OK;
-    kGemm[S](kind == DMP_OZ_FP16, p, ntiles, stream);
+    if (kind == DMP_MARKIDIS_FP16)
+        kTerms[S](p, ntiles, stream);
+    else
+        kGemm[S](kind == DMP_OZ_FP16, p, ntiles, stream);
     DMP_CHECK_HIP(hipGetLastError());
     return DMP_OK;
 }

@@ -637,7 +637,7 @@ int upload_group(GroupPlan& g, const double* const* H, double* const* P, const i
         pd[b] = d;
         if (g.kind == DMP_FP64_NATIVE) continue;
         const int KC = int(chunks_of(nb, g.kind));
-        const int64_t rbs = int64_t(KC) * g.S * kFragBytes;
+        const int64_t rbs = int64_t(KC) * planes_of(g.S, g.kind) * kFragBytes;
         SplitDesc sd{};
         sd.lda = nb;
         sd.R = nb;
@@ -1123,6 +1123,7 @@ int dmp_timing_read(int which, double* total_ms, long long* launches, double* op
 size_t dmp_purify_workspace_bytes(int n, int slices, dmp_kind kind) {
     if (n < 1) return 0;
     if (kind != DMP_FP64_NATIVE && (slices < 1 || slices > kMaxSlices)) return 0;
+    if (kind == DMP_MARKIDIS_FP16 && slices > kMaxTerms) return 0;
     size_t need = 0;
     const double* h = nullptr;
     double* p = nullptr;
@@ -1139,7 +1140,7 @@ int dmp_purify_ex(const double* H, int n, int nocc, double tol, int slices, dmp_
     DMP_CHECK(check_method_flags(method, flags));
     DMP_CHECK(check_kind_slices(kind, slices));
     DMP_CHECK(validate_purify_args(H, n, nocc, tol, max_iter, P));
-    if (kind != DMP_FP64_NATIVE && n > max_k_for_slices(slices)) {
+    if (kind != DMP_FP64_NATIVE && n > max_k_for(slices, kind)) {
         set_error("n = %d exceeds the exact INT32 range for %d slices", n, slices);
         return DMP_EINVAL;
     }

@@ -154,6 +154,16 @@ __device__ inline void digits_of(double a, int e, int (&d)[S]) {
     }
 }
 
+// Nearest FP16 value of x (ties to even), computed exactly in FP64: 11
+// significant bits for |x| >= 2^-14, a fixed quantum of 2^-24 below that (the
+// FP16 subnormals).  Scaled entries have |x| < 1, so nothing overflows.
+__device__ inline double nearest_fp16(double x) {
+    int ex = 0;
+    (void)frexp(x, &ex);
+    const int q = ex - 11 > -24 ? ex - 11 : -24;
+    return ldexp(rint(ldexp(x, -q)), q);
+}
+
 __device__ inline int exponent_of(uint64_t bits) {
     if (bits >= 0x7ff0000000000000ull) return kNonFiniteExp;
     int e = 0;
@@ -164,7 +174,9 @@ __device__ inline int exponent_of(uint64_t bits) {
 // Digits: one wavefront per fragment block (32 operand rows x CK reduction
 // elements); lane l owns operand row l % 32 and NE = CK / 2 consecutive
 // reduction elements.  A workgroup of 256 threads handles 4 blocks.
-template <int S, bool FP16>
+// HALVES (Markidis kind, S = 2, FP16): instead of digits, the high and low
+// FP16 parts of x = a 2^-e (|x| < 1): X0 = FP16[x], X1 = FP16[x - X0].
+template <int S, bool FP16, bool HALVES = false>
 __global__ __launch_bounds__(256) void k_digits(const SplitDesc* descs, int count,
                                                 SplitDesc one, const DevState* st) {
     constexpr int CK = FP16 ? 16 : 32;
@@ -202,11 +214,33 @@ __global__ __launch_bounds__(256) void k_digits(const SplitDesc* descs, int coun
         for (int i = 0; i < NE; ++i) v[i] = 0.0;
     }
 
+    uint8_t* base = d.planes + (int64_t(rb) * d.KC + kc) * int64_t(S) * kFragBytes + lane * 16;
+    if constexpr (HALVES) {
+        static_assert(S == 2 && FP16, "the Markidis split stores two FP16 planes");
+        uint32_t w[2][4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint16_t hb[2][2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const double x = e >= kNonFiniteExp ? 0.0 : ldexp(v[2 * q + t], -e);
+                const double hi = nearest_fp16(x);
+                const double lo = nearest_fp16(x - hi);
+                // both are FP16 values, so the conversions below are exact
+                hb[0][t] = __half_as_ushort(__float2half_rn(float(hi)));
+                hb[1][t] = __half_as_ushort(__float2half_rn(float(lo)));
+            }
+            w[0][q] = uint32_t(hb[0][0]) | (uint32_t(hb[0][1]) << 16);
+            w[1][q] = uint32_t(hb[1][0]) | (uint32_t(hb[1][1]) << 16);
+        }
+        *reinterpret_cast<uint4*>(base) = make_uint4(w[0][0], w[0][1], w[0][2], w[0][3]);
+        *reinterpret_cast<uint4*>(base + kFragBytes) = make_uint4(w[1][0], w[1][1], w[1][2], w[1][3]);
+        return;
+    }
     int dg[NE][S];
 #pragma unroll
     for (int i = 0; i < NE; ++i) digits_of<S>(v[i], e, dg[i]);
 
-    uint8_t* base = d.planes + (int64_t(rb) * d.KC + kc) * int64_t(S) * kFragBytes + lane * 16;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         uint4 out;
@@ -270,7 +304,10 @@ int launch_split(const SplitDesc& d, int S, dmp_kind kind, const DevState* st,
         k_fill_u64<<<(rp + 255) / 256, 256, 0, stream>>>(d.maxbits, rp, 0ull);
         if (d.K > 0) k_colmax<<<split_units_colmax(d.R, d.K), 256, 0, stream>>>(nullptr, 0, d, st);
     }
-    kDigits[S](kind == DMP_OZ_FP16, nullptr, 0, d, st, split_units_digits(d.R, d.KC), stream);
+    if (kind == DMP_MARKIDIS_FP16)
+        k_digits<2, true, true><<<split_units_digits(d.R, d.KC), 256, 0, stream>>>(nullptr, 0, d, st);
+    else
+        kDigits[S](kind == DMP_OZ_FP16, nullptr, 0, d, st, split_units_digits(d.R, d.KC), stream);
     DMP_CHECK_HIP(hipGetLastError());
     return DMP_OK;
 }
@@ -286,7 +323,10 @@ int launch_split_grouped_rowmax(const SplitDesc* descs_dev, int count, int units
 
 int launch_split_grouped_digits(const SplitDesc* descs_dev, int count, int units, int S,
                                 dmp_kind kind, const DevState* st, hipStream_t stream) {
-    if (units > 0) kDigits[S](kind == DMP_OZ_FP16, descs_dev, count, SplitDesc{}, st, units, stream);
+    if (units > 0 && kind == DMP_MARKIDIS_FP16)
+        k_digits<2, true, true><<<units, 256, 0, stream>>>(descs_dev, count, SplitDesc{}, st);
+    else if (units > 0)
+        kDigits[S](kind == DMP_OZ_FP16, descs_dev, count, SplitDesc{}, st, units, stream);
     DMP_CHECK_HIP(hipGetLastError());
     return DMP_OK;
 }

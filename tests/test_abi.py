@@ -38,6 +38,7 @@ def test_version_and_limits(lib):
     assert lib.dmp_version().decode().startswith("dmp")
     assert lib.dmp_max_slices(1) == lib.dmp_max_slices(2) >= 8
     assert lib.dmp_max_slices(0) == 0
+    assert lib.dmp_max_slices(3) == 4      # Markidis: terms
 
 
 def test_workspace_queries(lib):
@@ -49,6 +50,13 @@ def test_workspace_queries(lib):
     assert lib.dmp_gemm_workspace_bytes(10, 10, 10, 0, 1) == 0
     p = lib.dmp_purify_workspace_bytes(8192, 7, 1)
     assert p >= 2 * 8192 * 8192 * 8 + 2 * 7 * 8192 * 8192
+    # Markidis: two FP16 planes whatever the number of terms; at most 4 terms
+    m1 = lib.dmp_gemm_workspace_bytes(100, 70, 130, 1, 3)
+    assert m1 == lib.dmp_gemm_workspace_bytes(100, 70, 130, 4, 3)
+    assert m1 == lib.dmp_gemm_workspace_bytes(100, 70, 130, 2, 2)
+    assert lib.dmp_gemm_workspace_bytes(100, 70, 130, 5, 3) == 0
+    assert lib.dmp_purify_workspace_bytes(512, 5, 3) == 0
+    assert lib.dmp_purify_workspace_bytes(512, 3, 3) == lib.dmp_purify_workspace_bytes(512, 2, 2)
     n = (ctypes.c_int * 3)(128, 300, 1536)
     assert lib.dmp_purify_batched_workspace_bytes(3, n, 7, 1) > lib.dmp_purify_workspace_bytes(1536, 7, 1)
 
@@ -88,6 +96,10 @@ def test_argument_errors_without_device_work(lib):
     st = lib.dmp_purify(ctypes.c_void_p(8), 8, 4, 1e-8, 7, 9, 100, ctypes.c_void_p(16),
                         ctypes.byref(e), ctypes.byref(info), ws, 0, None)
     assert st == -1
+    # too many Markidis terms
+    st = lib.dmp_purify(ctypes.c_void_p(8), 8, 4, 1e-8, 5, 3, 100, ctypes.c_void_p(16),
+                        ctypes.byref(e), ctypes.byref(info), ws, 0, None)
+    assert st == -1 and b"terms" in lib.dmp_last_error()
     # unknown method or flag of the _ex entry points
     for method, flags in ((2, 0), (-1, 0), (1, 2), (0, 0x10)):
         st = lib.dmp_purify_ex(ctypes.c_void_p(8), 8, 4, 1e-8, 7, 1, 100, method, flags,
