@@ -210,9 +210,9 @@ def main():
     ws = torch.empty(lib.dmp_purify_workspace_bytes(n, a.slices, kind_id), dtype=torch.uint8,
                      device="cuda")
 
-    def run(kind, slices, out, wsb, method="canonical"):
+    def run(kind, slices, out, wsb, method="canonical", triangle=False):
         return dmp.purify(H, nocc, tol=tol, slices=slices, kind=kind, out=out, workspace=wsb,
-                          max_iter=a.max_iter, method=method)
+                          max_iter=a.max_iter, method=method, triangle=triangle)
 
     def accuracy(p, e):
         gpath = os.path.join(ROOT, "tests", "golden", "tb8192_reference.npz")
@@ -301,6 +301,15 @@ def main():
                       / FP64_PEAK_TFLOPS,
                       speedup_ozaki_vs_native=ms_n / ms_per_step,
                       max_dP_ozaki_vs_native=float(torch.max(torch.abs(P - Pn)).item()))
+        # the same upper-triangle saving for the baseline: rocBLAS dsyrk / dsyrkx
+        run("native", 0, Pn, wsn, triangle=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, en, infon = run("native", 0, Pn, wsn, triangle=True)
+        torch.cuda.synchronize()
+        ms_nt = (time.perf_counter() - t0) * 1e3
+        native.update(triangle_ms_per_purification=ms_nt, triangle_iters=infon["iters"],
+                      speedup_ozaki_vs_native_triangle=ms_nt / ms_per_step)
         del wsn, Pn
 
     # TRS4 (Sec. 3): same driver, fewer iterations; Ozaki against native
@@ -331,6 +340,11 @@ def main():
             trs4.update(native_ms=ms_tn, native_iters=infon["iters"],
                         native_products=infon["products"], speedup_vs_native=ms_tn / ms_t,
                         max_dP_vs_native=float(torch.max(torch.abs(P - Pn)).item()))
+            t0 = time.perf_counter()
+            run("native", 0, Pn, wsn, "trs4", triangle=True)
+            torch.cuda.synchronize()
+            ms_tnt = (time.perf_counter() - t0) * 1e3
+            trs4.update(native_triangle_ms=ms_tnt, speedup_vs_native_triangle=ms_tnt / ms_t)
             del wsn, Pn
 
     cpu = None

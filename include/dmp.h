@@ -83,7 +83,10 @@ typedef enum {
 
 /* Flags of the *_ex purification entry points. */
 enum {
-    DMP_REFINE_MCWEENY = 1   /* one FP64 step P <- 3P^2 - 2P^3 at the end    */
+    DMP_REFINE_MCWEENY = 1,  /* one FP64 step P <- 3P^2 - 2P^3 at the end    */
+    DMP_NATIVE_TRIANGLE = 2  /* DMP_FP64_NATIVE: products by rocBLAS dsyrk /
+                                dsyrkx on the upper triangle only (the saving
+                                the Ozaki kinds make), ignored otherwise    */
 };
 
 enum {
@@ -186,6 +189,8 @@ int dmp_purify(const double* H, int n, int nocc, double tol, int slices,
  *     non-finite or ran no iteration) one McWeeny step P <- 3P^2 - 2P^3 runs
  *     with rocBLAS FP64 products (Sec. 4.1); *E and info->E are then the
  *     refined energy and info->E_unrefined the energy before it.
+ *   flags & DMP_NATIVE_TRIANGLE (kind DMP_FP64_NATIVE only): X2 by rocBLAS
+ *     dsyrk and the second product by dsyrkx, upper triangle only.
  *   Other arguments, the workspace (dmp_purify_workspace_bytes covers every
  *   method and flag) and the blocking behaviour are those of dmp_purify.
  * ------------------------------------------------------------------- */

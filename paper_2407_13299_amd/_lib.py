@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(_PKG, "libdmp.so")
 KINDS = {"native": 0, "fp64": 0, "int8": 1, "fp16": 2, "markidis": 3}
 METHODS = {"canonical": 0, "trs4": 1}
 REFINE_MCWEENY = 1
+NATIVE_TRIANGLE = 2
 STOP_REASONS = {0: "converged", 1: "stagnated", 2: "max_iter", 3: "nonfinite"}
 DMP_OK, DMP_NOT_CONVERGED = 0, 1
 ERRORS = {-1: "DMP_EINVAL", -2: "DMP_ENONFINITE", -3: "DMP_EHIP", -4: "DMP_ENOMEM",

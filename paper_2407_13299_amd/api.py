@@ -117,9 +117,11 @@ def _method(method) -> int:
 
 
 def purify(H, nocc, tol=1e-8, slices=7, kind="int8", max_iter=200, out=None, stream=None,
-           workspace=None, method="canonical", refine=False):
+           workspace=None, method="canonical", refine=False, triangle=False):
     """Density-matrix purification (canonical or TRS4), optionally followed
-    by one FP64 McWeeny refinement step; returns (P, E, info dict)."""
+    by one FP64 McWeeny refinement step; returns (P, E, info dict).
+    ``triangle`` (kind 'native'): rocBLAS dsyrk / dsyrkx upper-triangle
+    products instead of full DGEMMs."""
     lib = _lib.load()
     _check_matrix(H, "H")
     n = H.shape[0]
@@ -131,7 +133,7 @@ def purify(H, nocc, tol=1e-8, slices=7, kind="int8", max_iter=200, out=None, str
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, H.device)
     e = ctypes.c_double(0.0)
     info = _lib.DmpInfo()
-    flags = _lib.REFINE_MCWEENY if refine else 0
+    flags = (_lib.REFINE_MCWEENY if refine else 0) | (_lib.NATIVE_TRIANGLE if triangle else 0)
     st = lib.dmp_purify_ex(_ptr(H), n, int(nocc), float(tol), int(slices), kd, int(max_iter),
                            _method(method), flags, _ptr(P), ctypes.byref(e), ctypes.byref(info),
                            _ptr(ws), ws.numel(), _stream(stream))

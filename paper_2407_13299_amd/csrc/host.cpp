@@ -112,6 +112,36 @@ int native_dgemm(hipStream_t stream, bool ta, bool tb, int m, int n, int k, cons
     return DMP_OK;
 }
 
+// Upper triangle (row-major) of symmetric products: rocBLAS is column-major,
+// so the row-major upper triangle is its lower one.  C = A A (A symmetric).
+int native_dsyrk_upper(hipStream_t stream, int n, const double* A, double* C) {
+    rocblas_handle h;
+    DMP_CHECK(blas_handle(stream, &h));
+    const double one = 1.0, zero = 0.0;
+    rocblas_status s = rocblas_dsyrk(h, rocblas_fill_lower, rocblas_operation_none, n, n, &one, A,
+                                     n, &zero, C, n);
+    if (s != rocblas_status_success) {
+        set_error("rocblas_dsyrk failed (%d)", int(s));
+        return DMP_EHIP;
+    }
+    return DMP_OK;
+}
+
+// C = A B for symmetric A, B whose product is symmetric (they commute): the
+// upper triangle by rocBLAS dsyrkx (A B^T = A B).
+int native_dsyrkx_upper(hipStream_t stream, int n, const double* A, const double* B, double* C) {
+    rocblas_handle h;
+    DMP_CHECK(blas_handle(stream, &h));
+    const double one = 1.0, zero = 0.0;
+    rocblas_status s = rocblas_dsyrkx(h, rocblas_fill_lower, rocblas_operation_none, n, n, &one,
+                                      A, n, B, n, &zero, C, n);
+    if (s != rocblas_status_success) {
+        set_error("rocblas_dsyrkx failed (%d)", int(s));
+        return DMP_EHIP;
+    }
+    return DMP_OK;
+}
+
 int check_kind_slices(dmp_kind kind, int slices) {
     if (kind != DMP_OZ_INT8 && kind != DMP_OZ_FP16 && kind != DMP_FP64_NATIVE &&
         kind != DMP_MARKIDIS_FP16) {

@@ -60,6 +60,8 @@ int split_units_digits(int R, int KC);
 struct GemmParams;
 int launch_ozgemm(int S, dmp_kind kind, const GemmParams& p, int ntiles, hipStream_t stream);
 
+int native_dsyrk_upper(hipStream_t stream, int n, const double* A, double* C);
+int native_dsyrkx_upper(hipStream_t stream, int n, const double* A, const double* B, double* C);
 int check_kind_slices(dmp_kind kind, int slices);
 int validate_purify_args(const double* H, int n, int nocc, double tol, int max_iter,
                          const double* P);

@@ -393,6 +393,24 @@ __global__ __launch_bounds__(256) void k_native_update(const PurDesc* pd, const 
     }
 }
 
+// Copy the upper triangle of a row-major n x n matrix onto its lower one
+// (32 x 32 tile pairs I <= J through LDS).
+__global__ __launch_bounds__(256) void k_mirror_upper(double* X, int n, const int2* pairs) {
+    __shared__ double t[32][33];
+    const int2 pr = pairs[blockIdx.x];
+    const int I = pr.x, J = pr.y;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int r = ty; r < 32; r += 8) {
+        const int i = I * 32 + r, j = J * 32 + tx;
+        t[r][tx] = (i < n && j < n) ? X[int64_t(i) * n + j] : 0.0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int i = J * 32 + r, j = I * 32 + tx;   // element (i, j) = (j, i) of the upper part
+        if (i < n && j < n && (I != J || j < i)) X[int64_t(i) * n + j] = t[tx][r];
+    }
+}
+
 // Native TRS4: T = ta P + tb X2 + tc I (full matrix).
 __global__ __launch_bounds__(256) void k_native_t(const PurDesc* pd, const DevState* states) {
     const PurDesc& d = pd[0];
@@ -886,8 +904,10 @@ int run_oz_groups(std::vector<GroupPlan>& groups, int max_iter, hipStream_t s,
 }
 
 // Native FP64 purification of one matrix (group of one), host-checked
-// every iteration.
-int run_native(GroupPlan& g, int max_iter, hipStream_t s, DevState& host) {
+// every iteration.  ``tri``: every product by rocBLAS dsyrk / dsyrkx on the
+// upper triangle only (the elementwise kernels read only that half; X2 is
+// mirrored because it is a full operand of the second product).
+int run_native(GroupPlan& g, int max_iter, hipStream_t s, DevState& host, bool tri) {
     const int n = g.max_n;
     const MatLayout& L = g.lay[0];
     PurDesc hd{};
@@ -900,7 +920,12 @@ int run_native(GroupPlan& g, int max_iter, hipStream_t s, DevState& host) {
         DMP_CHECK_HIP(hipStreamSynchronize(s));
         if (host.done) break;
         const double* P = host.iters & 1 ? L.Pw : hd.Pb[0];
-        DMP_CHECK(native_dgemm(s, false, false, n, n, n, P, n, P, n, L.X2, n));
+        if (tri) {
+            DMP_CHECK(native_dsyrk_upper(s, n, P, L.X2));
+            k_mirror_upper<<<np, 256, 0, s>>>(L.X2, n, g.pairs);
+        } else {
+            DMP_CHECK(native_dgemm(s, false, false, n, n, n, P, n, P, n, L.X2, n));
+        }
         // two host copies: each stays unmodified until the next iteration's sync
         PurDesc dsq = hd, dup = hd;
         dsq.part_begin = 0;
@@ -916,11 +941,17 @@ int run_native(GroupPlan& g, int max_iter, hipStream_t s, DevState& host) {
             DMP_CHECK_HIP(hipStreamSynchronize(s));
             if (host.gamma != 0.0) {
                 k_native_t<<<2048, 256, 0, s>>>(g.pd, g.st);
-                DMP_CHECK(native_dgemm(s, false, false, n, n, n, L.X2, n, L.T, n, L.X3, n));
+                if (tri)
+                    DMP_CHECK(native_dsyrkx_upper(s, n, L.X2, L.T, L.X3));
+                else
+                    DMP_CHECK(native_dgemm(s, false, false, n, n, n, L.X2, n, L.T, n, L.X3, n));
             }
         } else {
             k_finalize_coef<<<1, 256, 0, s>>>(g.pd, g.st);
-            DMP_CHECK(native_dgemm(s, false, false, n, n, n, L.X2, n, P, n, L.X3, n));
+            if (tri)
+                DMP_CHECK(native_dsyrkx_upper(s, n, L.X2, P, L.X3));
+            else
+                DMP_CHECK(native_dgemm(s, false, false, n, n, n, L.X2, n, P, n, L.X3, n));
         }
         DMP_CHECK_HIP(hipMemcpyAsync(g.pd, &dup, sizeof(PurDesc), hipMemcpyHostToDevice, s));
         k_native_update<<<np, 256, 0, s>>>(g.pd, g.st, g.pairs);
@@ -980,7 +1011,7 @@ int check_method_flags(int method, int flags) {
         set_error("unknown method %d", method);
         return DMP_EINVAL;
     }
-    if ((flags & ~DMP_REFINE_MCWEENY) != 0) {
+    if ((flags & ~(DMP_REFINE_MCWEENY | DMP_NATIVE_TRIANGLE)) != 0) {
         set_error("unknown flags 0x%x", flags);
         return DMP_EINVAL;
     }
@@ -1061,7 +1092,7 @@ int purify_many(int count, const double* const* H, const int* n, const int* nocc
     if (kind == DMP_FP64_NATIVE) {
         size_t off = 0;
         for (auto& g : groups) {
-            DMP_CHECK(run_native(g, max_iter, s, host_st[off]));
+            DMP_CHECK(run_native(g, max_iter, s, host_st[off], (flags & DMP_NATIVE_TRIANGLE) != 0));
             off += g.count;
         }
     } else {

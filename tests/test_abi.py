@@ -101,7 +101,7 @@ def test_argument_errors_without_device_work(lib):
                         ctypes.byref(e), ctypes.byref(info), ws, 0, None)
     assert st == -1 and b"terms" in lib.dmp_last_error()
     # unknown method or flag of the _ex entry points
-    for method, flags in ((2, 0), (-1, 0), (1, 2), (0, 0x10)):
+    for method, flags in ((2, 0), (-1, 0), (1, 4), (0, 0x10)):
         st = lib.dmp_purify_ex(ctypes.c_void_p(8), 8, 4, 1e-8, 7, 1, 100, method, flags,
                                ctypes.c_void_p(16), ctypes.byref(e), ctypes.byref(info), ws, 0,
                                None)

@@ -147,3 +147,19 @@ def test_full_size_tb_8192():
     comm = torch.linalg.norm(hd @ p - p @ hd).item()
     assert comm < 1e-8
     assert torch.equal(p, p.T)
+
+
+@pytest.mark.parametrize("method", ["canonical", "trs4"])
+def test_native_triangle_products(method):
+    """rocBLAS dsyrk / dsyrkx upper-triangle products give the full-DGEMM
+    native result (same iterations, P within rounding) on an uneven size."""
+    h = tight_binding_hamiltonian(5, 6, 7, seed=12)
+    n = h.shape[0]
+    nocc = n // 4
+    p0, e0, i0 = gpu_purify(h, nocc, tol=1e-10, kind="native", method=method)
+    p1, e1, i1 = gpu_purify(h, nocc, tol=1e-10, kind="native", method=method, triangle=True)
+    p_ref, e_ref, _, _ = projector.eigh_projector(h, nocc)
+    assert abs(i1["iters"] - i0["iters"]) <= 1 and i1["stop"] == "converged"
+    assert np.max(np.abs(p1 - p0)) < 1e-11
+    assert np.max(np.abs(p1 - p_ref)) < TOL_P and abs(e1 - e_ref) < TOL_E
+    assert np.array_equal(p1, p1.T)
