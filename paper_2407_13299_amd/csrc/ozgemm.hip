@@ -59,6 +59,10 @@ __device__ inline void wait_lgkm0() {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+// Fourth word of a raw buffer descriptor on gfx950 (32-bit data format,
+// no swizzle, no index stride).
+constexpr int kBufferWord3 = 0x00020000;
+
 __device__ inline double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
@@ -86,28 +90,41 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
     const DevState* st = p.states ? p.states + d.state_index : nullptr;
     if (st != nullptr && st->done) return;
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
     const int wm = wave >> 1, wn = wave & 1;
     const int I = tile.I, J = tile.J;
     const int KC = d.KC;
     const int64_t a_rb = d.a_rb_stride, b_rb = d.b_rb_stride;
-    // left operand row blocks 4I..4I+3, right operand row blocks 2J, 2J+1
-    const uint8_t* a0 = d.pa + int64_t(4 * I) * a_rb + lane * 16;
-    const uint8_t* b0 = d.pb + int64_t(2 * J) * b_rb + lane * 16;
-
-    // piece i of this thread: block i * WAVES + wave (wave-uniform), lane.
-    // Every wavefront issues PER loads per chunk (a block index past the end
-    // re-reads block 0 and is not stored), so the count of loads in flight is
-    // the same on every path and the compiler's waits stay exact.
+    // Piece i of this thread: block i * WAVES + wave (wave-uniform), lane.
+    // Block b of a chunk is digit plane b % S of operand row block b / S (left
+    // operand row blocks 4I..4I+3, then right operand row blocks 2J, 2J+1).
+    // Loads are buffer loads: one descriptor per piece holding the base of
+    // its row block (wave-uniform), the per-chunk offset in a scalar register
+    // and the lane's 16 bytes as the only vector offset, so no per-lane
+    // 64-bit address arithmetic runs in the loop.  Every wavefront issues
+    // PER loads per chunk (a block index past the end re-reads block 0 and is
+    // not stored), so the count of loads in flight is the same on every path
+    // and the compiler's waits stay exact.
+    __amdgpu_buffer_rsrc_t rsrc[PER];
+    int poff[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int blk0 = i * WAVES + wave;
+        const int blk = blk0 < BLOCKS ? blk0 : 0;
+        const int ob = blk / S;
+        poff[i] = (blk % S) * kFragBytes;
+        const uint8_t* base = ob < 4 ? d.pa + int64_t(4 * I + ob) * a_rb
+                                     : d.pb + int64_t(2 * J + ob - 4) * b_rb;
+        const int64_t rb = ob < 4 ? a_rb : b_rb;   // bytes of one row block
+        rsrc[i] = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(base), 0, int(rb),
+                                                    kBufferWord3);
+    }
     auto gload = [&](int kc, v4i (&r)[PER]) __attribute__((always_inline)) {
 #pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int blk0 = i * WAVES + wave;
-            const int blk = blk0 < BLOCKS ? blk0 : 0;
-            const int ob = blk / S, s = blk % S;
-            const uint8_t* src = ob < 4 ? a0 + int64_t(ob) * a_rb : b0 + int64_t(ob - 4) * b_rb;
-            r[i] = *reinterpret_cast<const v4i*>(src + (int64_t(kc) * S + s) * kFragBytes);
-        }
+        for (int i = 0; i < PER; ++i)
+            r[i] = __builtin_amdgcn_raw_buffer_load_b128(rsrc[i], lane * 16,
+                                                         kc * (S * kFragBytes) + poff[i], 0);
     };
     auto lstore = [&](int buf, const v4i (&r)[PER]) __attribute__((always_inline)) {
 #pragma unroll
