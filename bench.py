@@ -187,7 +187,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU "
-                                   "sharding is described in DESIGN.md but not built"}))
+                                   "paths are not built"}))
         sys.exit(2)
     if a.workload == "batched_64":
         bench_batched(a)
