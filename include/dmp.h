@@ -203,7 +203,10 @@ int dmp_purify_ex(const double* H, int n, int nocc, double tol, int slices,
  * Batched purification: count independent Hamiltonians of (possibly)
  * different sizes n[b] with nocc[b] occupied levels, sharing tol, kind and
  * max_iter.  slices <= 0 picks S per matrix from the tuned table (see
- * dmp_autotune_slices).  H and P are HOST arrays of device pointers; n,
+ * dmp_autotune_slices); matrices that need fewer slices than the batch's
+ * largest count then run with that count (never less accurate) when they
+ * carry under a quarter of the batch's n^3 work, so the batch stays one
+ * group of launches.  info[b].slices reports the count used.  H and P are HOST arrays of device pointers; n,
  * nocc are host arrays; E (host, length count) and info (host, length
  * count, may be NULL) receive the per-matrix results.  Every phase of an
  * iteration runs as one grouped launch over all unfinished matrices, and

@@ -1,4 +1,5 @@
 // Batched purification entry point and the slice-count table.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -23,13 +24,46 @@ int dmp_autotune_slices(int n, double target, dmp_kind kind) {
     return kMaxSlices;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Slice count per matrix of a batch.  slices > 0: that count for every
+// matrix.  Otherwise the tuned table's count per matrix; matrices that need
+// fewer slices than the batch maximum then run with the maximum (a larger S
+// is always at least as accurate) when they carry under a quarter of the
+// batch's n^3 work, so that the batch runs as one group of launches instead
+// of one group per slice count.
+void batch_slices(int count, const int* n, int slices, dmp_kind kind, std::vector<int>& s) {
+    s.assign(count, 0);
+    if (kind == DMP_FP64_NATIVE) return;
+    int smax = 0;
+    for (int b = 0; b < count; ++b) {
+        s[b] = slices > 0 ? slices : dmp_autotune_slices(n[b], kTunedTarget, kind);
+        smax = std::max(smax, s[b]);
+    }
+    if (slices > 0 || count < 2) return;
+    double low = 0.0, all = 0.0;
+    for (int b = 0; b < count; ++b) {
+        const double w = double(n[b]) * n[b] * n[b];
+        all += w;
+        if (s[b] < smax) low += w;
+    }
+    if (low >= 0.25 * all) return;
+    for (int b = 0; b < count; ++b)
+        if (n[b] <= max_k_for(smax, kind)) s[b] = smax;
+}
+
+}  // namespace
+
+extern "C" {
+
 size_t dmp_purify_batched_workspace_bytes(int count, const int* n, int slices, dmp_kind kind) {
     if (count < 1 || !n) return 0;
-    std::vector<int> s(count);
-    for (int b = 0; b < count; ++b) {
+    for (int b = 0; b < count; ++b)
         if (n[b] < 1) return 0;
-        s[b] = slices > 0 ? slices : dmp_autotune_slices(n[b], kTunedTarget, kind);
-    }
+    std::vector<int> s;
+    batch_slices(count, n, slices, kind, s);
     std::vector<const double*> h(count, nullptr);
     std::vector<double*> p(count, nullptr);
     std::vector<int> nocc(count, 0);
@@ -49,10 +83,11 @@ int dmp_purify_batched_ex(int count, const double* const* H, const int* n, const
         set_error("bad batch arguments");
         return DMP_EINVAL;
     }
-    std::vector<int> s(count);
-    for (int b = 0; b < count; ++b) {
+    for (int b = 0; b < count; ++b)
         DMP_CHECK(validate_purify_args(H[b], n[b], nocc[b], tol, max_iter, P[b]));
-        s[b] = kind == DMP_FP64_NATIVE ? 0 : (slices > 0 ? slices : dmp_autotune_slices(n[b], kTunedTarget, kind));
+    std::vector<int> s;
+    batch_slices(count, n, slices, kind, s);
+    for (int b = 0; b < count; ++b) {
         if (kind != DMP_FP64_NATIVE) {
             DMP_CHECK(check_kind_slices(kind, s[b]));
             if (n[b] > max_k_for(s[b], kind)) {

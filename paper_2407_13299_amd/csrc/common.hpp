@@ -178,6 +178,11 @@ struct GemmParams {
     double* partials;       // [tiles][kPartials] (purification modes)
     const DevState* states; // nullable; tiles of finished matrices exit
     int mode;
+    // 0: give every XCD a contiguous slice of the tile list (L2 reuse of one
+    // matrix's panels); 1: plain block order, for tile lists sorted from the
+    // most to the least work (the hardware's round-robin over XCDs then
+    // spreads every cost class evenly)
+    int spread;
 };
 
 }  // namespace dmp

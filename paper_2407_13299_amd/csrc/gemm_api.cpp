@@ -254,8 +254,12 @@ int dmp_ozaki_gemm_batched(int count, const int* m, const int* n, const int* k,
         q.ldc = n[b];
         q.state_index = -1;
         md[b] = q;
-        append_tiles(tiles, tile_rows(m[b]), tile_cols(n[b]), false, uint32_t(b));
     }
+    // tiles of the longest reductions first (dispatched in that order)
+    std::vector<int> order(count);
+    for (int b = 0; b < count; ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return k[x] > k[y]; });
+    for (int b : order) append_tiles(tiles, tile_rows(m[b]), tile_cols(n[b]), false, uint32_t(b));
     Tile* t_dev = c.take<Tile>(tiles.size());
     DMP_CHECK_HIP(hipMemcpyAsync(sd_dev, sa.data(), count * sizeof(SplitDesc), hipMemcpyHostToDevice, s));
     DMP_CHECK_HIP(hipMemcpyAsync(md_dev, md.data(), count * sizeof(MatDesc), hipMemcpyHostToDevice, s));
@@ -271,6 +275,7 @@ int dmp_ozaki_gemm_batched(int count, const int* m, const int* n, const int* k,
     p.tiles = t_dev;
     p.descs = md_dev;
     p.mode = EPI_STORE;
+    p.spread = count > 1 ? 1 : 0;
     DMP_CHECK(launch_ozgemm(slices, kind, p, int(tiles.size()), s));
     // the host vectors must outlive the asynchronous copies
     DMP_CHECK_HIP(hipStreamSynchronize(s));

@@ -84,7 +84,8 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
     // XCDs in turn; give every XCD one contiguous slice of the tile list.
     const int nb = gridDim.x, b = blockIdx.x;
     const int xcd = b & 7, q = nb >> 3, rem = nb & 7, loc = b >> 3;
-    const int t = (xcd < rem) ? xcd * (q + 1) + loc : rem * (q + 1) + (xcd - rem) * q + loc;
+    const int t = p.spread ? b
+                           : (xcd < rem) ? xcd * (q + 1) + loc : rem * (q + 1) + (xcd - rem) * q + loc;
     const Tile tile = p.tiles[t];
     const MatDesc d = p.descs ? p.descs[tile.mat] : p.one;
     const DevState* st = p.states ? p.states + d.state_index : nullptr;

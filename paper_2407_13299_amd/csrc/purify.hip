@@ -623,8 +623,25 @@ int upload_group(GroupPlan& g, const double* const* H, double* const* P, const i
     std::vector<SplitDesc> sp0(cnt), sp1(cnt), sx(cnt), st0(cnt), st1(cnt);
     std::vector<MatDesc> q0(cnt), q1(cnt), u0(cnt), u1(cnt);
     std::vector<Tile> tiles;
-    int pbeg = 0, urow = 0, udig = 0;
+    int urow = 0, udig = 0;
     g.max_n = 0;
+    // tile list: matrices from the largest to the smallest (each matrix's
+    // tiles contiguous, so its partials form one range)
+    std::vector<int> order(cnt);
+    for (int b = 0; b < cnt; ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return n[g.idx[x]] > n[g.idx[y]]; });
+    std::vector<int> part_begin(cnt, 0), part_end(cnt, 0);
+    if (g.kind != DMP_FP64_NATIVE) {
+        int pbeg = 0;
+        for (int b : order) {
+            const int nb = n[g.idx[b]];
+            part_begin[b] = pbeg;
+            pbeg += oz_tiles(nb);
+            part_end[b] = pbeg;
+            append_tiles(tiles, tile_rows(nb), tile_cols(nb), true, uint32_t(b));
+        }
+    }
     for (int b = 0; b < cnt; ++b) {
         const int m = g.idx[b], nb = n[m];
         const MatLayout& L = g.lay[b];
@@ -647,10 +664,8 @@ int upload_group(GroupPlan& g, const double* const* H, double* const* P, const i
             d.part_begin = 0;
             d.part_end = 0;   // set per phase by the native driver
         } else {
-            d.part_begin = pbeg;
-            pbeg += oz_tiles(nb);
-            d.part_end = pbeg;
-            append_tiles(tiles, tile_rows(nb), tile_cols(nb), true, uint32_t(b));
+            d.part_begin = part_begin[b];
+            d.part_end = part_end[b];
         }
         pd[b] = d;
         if (g.kind == DMP_FP64_NATIVE) continue;
@@ -790,6 +805,7 @@ int launch_oz_iteration(GroupPlan& g, int par, hipStream_t s,
     p.states = g.st;
     const bool trs4 = g.method == DMP_TRS4;
     p.mode = trs4 ? EPI_SQUARE_TRS4 : EPI_SQUARE;
+    p.spread = g.count > 1 ? 1 : 0;
     DMP_CHECK(timed_gemm(g, p, 0, ops, s, timers));
     if (trs4)
         k_finalize_trs4<<<g.count, 256, 0, s>>>(g.pd, g.st);

@@ -50,8 +50,13 @@ def test_batched_autotuned_slices_and_mixed_models():
     noccs.append(350)
     Ps, Es, infos = dmp.purify_batched([dev(h) for h in hs], noccs, tol=1e-9, slices=0)
     torch.cuda.synchronize()
-    for h, nocc, p, e, info in zip(hs, noccs, Ps, Es, infos):
-        assert info["slices"] == dmp.autotune_slices(h.shape[0], 1e-10)
+    tuned = [dmp.autotune_slices(h.shape[0], 1e-10) for h in hs]
+    work = [h.shape[0] ** 3 for h in hs]
+    low = sum(w for w, t in zip(work, tuned) if t < max(tuned))
+    for h, nocc, p, e, info, t in zip(hs, noccs, Ps, Es, infos, tuned):
+        # the tuned count is a minimum; a minority of the work joins the largest count
+        assert info["slices"] >= t
+        assert info["slices"] == (max(tuned) if low < 0.25 * sum(work) else t)
         assert info["stop"] == "converged"
         p_ref, e_ref, _, _ = projector.eigh_projector(h, nocc)
         assert np.max(np.abs(p.cpu().numpy() - p_ref)) < 1e-10
