@@ -141,3 +141,23 @@ def test_deterministic():
     c1 = run(a, b, 7, "int8")
     c2 = run(a, b, 7, "int8")
     assert np.array_equal(c1, c2)
+
+
+@pytest.mark.parametrize("kind", ["int8", "fp16"])
+def test_int32_group_sums_at_the_reduction_limit(kind):
+    """k at the largest value the host accepts for S = 5, every entry split
+    into the digits (-63, -128, -128, -128, -128): all slice products share a
+    sign and the top group sum reaches 80 % of the INT32 range; the result is
+    still bit-identical to the oracle's integer model.  One more element is
+    rejected."""
+    s = 5
+    k = (2 ** 31 - 1) // (s * 16384)
+    v = -(63.5 + 0.5 / 256 + 0.5 / 256 ** 2 + 0.5 / 256 ** 3 + 0.5 / 256 ** 4)
+    _, d = ozaki.split_rows(np.full((1, 1), v), s)
+    assert list(d[:, 0, 0]) == [-63, -128, -128, -128, -128]
+    a = np.full((40, k), v)
+    b = np.full((k, 36), v)
+    b[:, 3] *= 0.5          # a second column exponent
+    assert np.array_equal(run(a, b, s, kind), ozaki.ozaki_gemm(a, b, s))
+    with pytest.raises(dmp.DmpError):
+        dmp.ozaki_gemm(dev(np.full((4, k + 1), v)), dev(np.full((k + 1, 4), v)), slices=s, kind=kind)

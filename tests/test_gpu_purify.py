@@ -163,3 +163,16 @@ def test_native_triangle_products(method):
     assert np.max(np.abs(p1 - p0)) < 1e-11
     assert np.max(np.abs(p1 - p_ref)) < TOL_P and abs(e1 - e_ref) < TOL_E
     assert np.array_equal(p1, p1.T)
+
+
+def test_fully_degenerate_spectrum():
+    """H = c I: every P with tr P = nocc has the exact energy c nocc, so the
+    iteration stops at once with that energy; tr(P - P^2) > 0 reports that
+    the result is not a projector (no gap to separate occupied levels)."""
+    n, nocc, c = 96, 30, -0.25
+    h = c * np.eye(n)
+    p, e, info = gpu_purify(h, nocc, tol=1e-10, slices=7)
+    assert info["stop"] == "converged"
+    assert abs(e - c * nocc) < 1e-12
+    assert abs(info["trace"] - nocc) < 1e-9
+    assert info["idem"] > 1.0
