@@ -35,7 +35,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--slices", type=int, default=7)
+    ap.add_argument("--slices", type=int, default=None,
+                    help="slices (default 7; batched_64: 0 = the tuned table)")
     ap.add_argument("--kind", default="int8", choices=["int8", "fp16"])
     ap.add_argument("--workload", default="tb_8192")
     ap.add_argument("--native-steps", type=int, default=1)
@@ -185,6 +186,8 @@ def bench_adjoint(a):
 
 def main():
     a = parse()
+    if a.slices is None:
+        a.slices = 0 if a.workload == "batched_64" else 7
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU "
                                    "paths are not built"}))

@@ -3,9 +3,8 @@ import numpy as np
 import pytest
 
 from oracle import projector
-from paper_2407_13299_amd.workloads import (batched_spectrum_sizes,
-                                            spectrum_hamiltonian,
-                                            tight_binding_hamiltonian)
+from paper_2407_13299_amd.workloads import (spectrum_hamiltonian,
+                                            tight_binding_hamiltonian, workload)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -63,14 +62,17 @@ def test_batched_autotuned_slices_and_mixed_models():
         assert abs(e - e_ref) < 1e-8
 
 
-def test_batched_workload_sample():
-    """Eight matrices of the 64-matrix workload (sizes from its generator)."""
-    sizes = [int(s) for s in batched_spectrum_sizes(64, seed=3)[:8]]
-    hs = [spectrum_hamiltonian(n, n // 2, seed=1000 + b)[0] for b, n in enumerate(sizes)]
-    noccs = [n // 2 for n in sizes]
-    Ps, Es, infos = dmp.purify_batched([dev(h) for h in hs], noccs, tol=1e-8, slices=7)
+def test_batched_full_workload():
+    """All 64 matrices of the batched workload in the configuration the
+    benchmark times (tol 1e-8, slice counts from the tuned table), each against
+    its eigendecomposition projector."""
+    w = workload("batched_64")
+    Ps, Es, infos = dmp.purify_batched([dev(h) for h in w["H"]], w["nocc"], tol=w["tol"],
+                                       slices=0)
     torch.cuda.synchronize()
-    for h, nocc, p, e, info in zip(hs, noccs, Ps, Es, infos):
+    assert len(Ps) == 64
+    for h, nocc, p, e, info in zip(w["H"], w["nocc"], Ps, Es, infos):
+        assert info["stop"] == "converged", info
         p_ref, e_ref, _, _ = projector.eigh_projector(h, nocc)
         assert np.max(np.abs(p.cpu().numpy() - p_ref)) < 1e-10
         assert abs(e - e_ref) < 1e-8
