@@ -265,7 +265,8 @@ int dmp_tape_coefficients(const dmp_tape* tape, double* c, double* t1, double* t
 void dmp_tape_free(dmp_tape* tape);
 
 /* ---------------------------------------------------------------------
- * Kernel timing (instrumentation).  While enabled, the purification entry
+ * Kernel timing (instrumentation; process-wide state, not for concurrent
+ * use from several host threads).  While enabled, the purification entry
  * points record a HIP event pair on the caller's stream around every
  * slice-GEMM launch (and launch without graph capture), and accumulate the
  * durations once each batch of iterations has completed.

@@ -518,12 +518,7 @@ int dmp_purify_fwd_tape(const double* H, int n, int nocc, double tol, int slices
         const hipError_t e = hipMemcpyAsync(d, src, size_t(n) * n * sizeof(double),
                                             hipMemcpyDefault, s);
         if (e != hipSuccess) {
-            hipPointerAttribute_t as{}, ad{};
-            const hipError_t ea = hipPointerGetAttributes(&as, src);
-            const hipError_t eb = hipPointerGetAttributes(&ad, d);
-            set_error("checkpoint copy failed: %s (src %p type %d err %d, dst %p type %d err %d, %zu bytes)",
-                      hipGetErrorString(e), (const void*)src, int(as.type), int(ea), (void*)d,
-                      int(ad.type), int(eb), size_t(n) * n * sizeof(double));
+            set_error("checkpoint copy failed: %s", hipGetErrorString(e));
             return DMP_EHIP;
         }
         return DMP_OK;

@@ -69,12 +69,13 @@ int cached_tiles(int tm, int tn, bool upper, const Tile** out) {
     return DMP_OK;
 }
 
+// One rocBLAS handle per device and host thread: a handle carries its stream,
+// so threads that share one would race between setting the stream and the
+// call.  Handles live until the process ends.
 int blas_handle(hipStream_t stream, rocblas_handle* out) {
-    static std::mutex mu;
-    static std::map<int, rocblas_handle> handles;
+    static thread_local std::map<int, rocblas_handle> handles;
     int dev = 0;
     DMP_CHECK_HIP(hipGetDevice(&dev));
-    std::lock_guard<std::mutex> lock(mu);
     auto it = handles.find(dev);
     rocblas_handle h;
     if (it == handles.end()) {
