@@ -176,3 +176,54 @@ def test_fully_degenerate_spectrum():
     assert abs(e - c * nocc) < 1e-12
     assert abs(info["trace"] - nocc) < 1e-9
     assert info["idem"] > 1.0
+
+
+@pytest.mark.parametrize("method", ["canonical", "trs4"])
+def test_graph_replays_equal_eager_launches(method, monkeypatch):
+    """Iterations run from a captured hipGraph, replayed many times per call,
+    give the same iterates bit for bit as eager launches."""
+    h = tight_binding_hamiltonian(4, 5, 6, seed=13)
+    nocc = h.shape[0] // 4
+    p_graph, e_graph, i_graph = gpu_purify(h, nocc, tol=1e-10, slices=7, method=method)
+    monkeypatch.setenv("DMP_NO_GRAPH", "1")
+    p_eager, e_eager, i_eager = gpu_purify(h, nocc, tol=1e-10, slices=7, method=method)
+    assert i_graph["iters"] == i_eager["iters"] > 8
+    assert np.array_equal(p_graph, p_eager) and e_graph == e_eager
+
+
+def test_side_stream_and_concurrent_threads():
+    """A purification on a side stream, and two host threads purifying at the
+    same time on their own streams (Ozaki and native kinds), match the
+    results of the default stream."""
+    import threading
+    hs = [tight_binding_hamiltonian(4, 4, 5, seed=20 + i) for i in range(2)]
+    nocc = hs[0].shape[0] // 4
+    ref = [gpu_purify(h, nocc, tol=1e-10, slices=7, kind=k) for h, k in zip(hs, ("int8", "native"))]
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        p, e, _ = dmp.purify(dev(hs[0]), nocc, tol=1e-10, slices=7, stream=side)
+    side.synchronize()
+    assert np.array_equal(p.cpu().numpy(), ref[0][0]) and e == ref[0][1]
+    out = [None, None]
+    errors = []
+
+    def work(i, kind):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                hd = dev(hs[i])
+                for _ in range(3):
+                    p, e, _ = dmp.purify(hd, nocc, tol=1e-10, slices=7, kind=kind, stream=s)
+                s.synchronize()
+                out[i] = (p.cpu().numpy(), e)
+        except Exception as exc:          # reported below
+            errors.append(exc)
+
+    th = [threading.Thread(target=work, args=(i, k)) for i, k in enumerate(("int8", "native"))]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errors, errors
+    for i in range(2):
+        assert np.array_equal(out[i][0], ref[i][0]) and out[i][1] == ref[i][1]
