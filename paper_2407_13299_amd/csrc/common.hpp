@@ -95,6 +95,9 @@ struct MatDesc {
     const double* H;       // Hamiltonian
     double* out;           // output matrix
     double* out2;          // second output (mirror target / spare)
+    uint64_t* rowmax;      // nullable (purification modes): atomicMax of the
+                           // bit pattern of |out_ij| into rowmax[i], for the
+                           // next split; zeroed beforehand by the caller
     int64_t a_rb_stride;   // bytes between 32-row blocks of pa
     int64_t b_rb_stride;   // bytes between 32-row blocks of pb
     int M, N, KC;          // rows, columns, reduction chunks
@@ -136,6 +139,8 @@ struct SplitDesc {
     uint64_t* maxbits;  // [Rp] bit pattern of max |row|
     int* expo;          // [Rp] exponents
     uint8_t* planes;    // digit planes
+    uint64_t* clear;    // nullable: rows [0, R padded) of this array are zeroed
+                        // (the row maxima the next product accumulates)
     int ub_rowmax;      // first k_rowmax unit of this matrix (grouped)
     int ub_digits;      // first k_digits unit of this matrix (grouped)
     int state_index;    // -1: no state

@@ -244,6 +244,16 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
     }
     const int n = d.M;
     double s0 = 0.0, s1 = 0.0;
+    // row maxima of the output for the next split (purification modes):
+    // bit patterns of |value| (their integer order is the numeric order, a
+    // NaN above an infinity), per element of this lane (row) and per column
+    uint64_t rmax[16];
+    uint64_t cmax = 0;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) rmax[v] = 0;
+    auto absbits = [](double x) __attribute__((always_inline)) {
+        return static_cast<uint64_t>(__double_as_longlong(x)) & 0x7fffffffffffffffull;
+    };
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         const int row = row0 + (v >> 2) * 8 + (v & 3);
@@ -270,25 +280,52 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
         const double mult = diag ? 1.0 : 2.0;
         const int64_t ij = int64_t(row) * n + col, ji = int64_t(col) * n + row;
         const double pij = d.P[ij];
+        double w;
         if (mode == EPI_SQUARE) {
-            d.out[ij] = c;
-            if (!diag) d.out[ji] = c;
+            w = c;
             if (diag) s0 += pij - c;
             s1 += mult * c * ((diag ? 1.0 : 0.0) - pij);
         } else if (mode == EPI_SQUARE_TRS4) {
             // tr F = sum_ij X2_ij (4 X_ij - 3 X2_ij), tr G = sum_ij (X_ij - X2_ij)^2
-            d.out[ij] = c;
-            if (!diag) d.out[ji] = c;
+            w = c;
             const double r = pij - c;
             s0 += mult * c * (4.0 * pij - 3.0 * c);
             s1 += mult * r * r;
         } else {  // EPI_UPDATE
-            const double nv = alpha * pij + beta * d.X2[ij] + gamma * c;
-            d.out[ij] = nv;
-            if (!diag) d.out[ji] = nv;
-            s0 += mult * nv * d.H[ij];
-            if (diag) s1 += nv;
+            w = alpha * pij + beta * d.X2[ij] + gamma * c;
+            s0 += mult * w * d.H[ij];
+            if (diag) s1 += w;
         }
+        d.out[ij] = w;
+        if (!diag) d.out[ji] = w;
+        const uint64_t b = absbits(w);
+        rmax[v] = b;                       // element (row, col) of row ``row``
+        cmax = b > cmax ? b : cmax;        // its mirror (col, row) of row ``col``
+    }
+    if (mode != EPI_STORE && d.rowmax != nullptr) {
+        // rows: the 32 lanes of a half share the 16 rows of their v values
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+#pragma unroll
+            for (int off = 1; off < 32; off <<= 1) {
+                const uint64_t o = static_cast<uint64_t>(__shfl_xor(static_cast<long long>(rmax[v]), off, 64));
+                rmax[v] = o > rmax[v] ? o : rmax[v];
+            }
+        }
+        const int myv = lane & 31;
+        uint64_t mine = 0;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) mine = (myv == v) ? rmax[v] : mine;
+        const int myrow = row0 + (myv >> 2) * 8 + (myv & 3);
+        if (myv < 16 && myrow < n && mine != 0)
+            atomicMax(reinterpret_cast<unsigned long long*>(d.rowmax) + myrow,
+                      static_cast<unsigned long long>(mine));
+        // columns: both halves hold rows of the same column
+        const uint64_t o = static_cast<uint64_t>(__shfl_xor(static_cast<long long>(cmax), 32, 64));
+        cmax = o > cmax ? o : cmax;
+        if (lane < 32 && col < n && cmax != 0)
+            atomicMax(reinterpret_cast<unsigned long long*>(d.rowmax) + col,
+                      static_cast<unsigned long long>(cmax));
     }
     if (mode != EPI_STORE) {
         s0 = wave_sum(s0);

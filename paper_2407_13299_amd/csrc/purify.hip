@@ -682,17 +682,24 @@ int upload_group(GroupPlan& g, const double* const* H, double* const* P, const i
         sd.state_index = b;
         urow += split_units_rowmax(nb);
         udig += split_units_digits(nb, KC);
+        // Row maxima: those of P come from the update's epilogue (of P0 from
+        // k_rowmax), those of X2 from the square's; each array is zeroed by
+        // the split that runs just before its producer.
         sd.A = P[m];
         sd.maxbits = L.maxP;
         sd.expo = L.expP;
         sd.planes = L.planesP;
+        sd.clear = L.maxX;
         sp0[b] = sd;
         sd.A = L.Pw;
         sp1[b] = sd;
         // TRS4: T = ta P + tb X2 + tc I, split into P's planes (free once the
-        // square has run)
+        // square has run); its row maxima (k_rowmax) go to X2's array, free
+        // once X2 is split
         sd.A = P[m];
         sd.A2 = L.X2;
+        sd.maxbits = L.maxX;
+        sd.clear = nullptr;
         st0[b] = sd;
         sd.A = L.Pw;
         st1[b] = sd;
@@ -701,6 +708,7 @@ int upload_group(GroupPlan& g, const double* const* H, double* const* P, const i
         sd.maxbits = L.maxX;
         sd.expo = L.expX;
         sd.planes = L.planesX;
+        sd.clear = L.maxP;
         sx[b] = sd;
         MatDesc md{};
         md.a_rb_stride = rbs;
@@ -718,6 +726,7 @@ int upload_group(GroupPlan& g, const double* const* H, double* const* P, const i
         md.ea = L.expP;
         md.eb = L.expP;
         md.out = L.X2;
+        md.rowmax = L.maxX;
         md.P = P[m];
         q0[b] = md;
         md.P = L.Pw;
@@ -725,6 +734,7 @@ int upload_group(GroupPlan& g, const double* const* H, double* const* P, const i
         // update: A = planes of X2, B = planes of P; P' into the other buffer
         md.pa = L.planesX;
         md.ea = L.expX;
+        md.rowmax = L.maxP;
         md.P = P[m];
         md.out = L.Pw;
         u0[b] = md;
@@ -763,7 +773,11 @@ int upload_group(GroupPlan& g, const double* const* H, double* const* P, const i
 }
 
 int launch_init(GroupPlan& g, double tol, int max_iter, hipStream_t s) {
-    return launch_purify_init(g.pd, g.st, g.count, g.max_n, tol, max_iter, s);
+    DMP_CHECK(launch_purify_init(g.pd, g.st, g.count, g.max_n, tol, max_iter, s));
+    // row maxima of P0 (later iterates get theirs from the update's epilogue)
+    if (g.kind != DMP_FP64_NATIVE)
+        DMP_CHECK(launch_split_grouped_rowmax(g.splitP[0], g.count, g.units_rowmax, g.st, s));
+    return DMP_OK;
 }
 
 double gemm_ops(const GroupPlan& g, const int* n) {
@@ -796,7 +810,7 @@ int timed_gemm(GroupPlan& g, const GemmParams& p, int which, double ops, hipStre
 // One Ozaki iteration of the whole group with iterate parity ``par``.
 int launch_oz_iteration(GroupPlan& g, int par, hipStream_t s,
                         std::vector<PendingTimer>* timers = nullptr, double ops = 0.0) {
-    DMP_CHECK(launch_split_grouped_rowmax(g.splitP[par], g.count, g.units_rowmax, g.st, s));
+    // the row maxima of P come from the previous update's epilogue
     DMP_CHECK(launch_split_grouped_digits(g.splitP[par], g.count, g.units_digits, g.S, g.kind, g.st, s));
     GemmParams p{};
     p.tiles = g.tiles;
@@ -811,7 +825,7 @@ int launch_oz_iteration(GroupPlan& g, int par, hipStream_t s,
         k_finalize_trs4<<<g.count, 256, 0, s>>>(g.pd, g.st);
     else
         k_finalize_coef<<<g.count, 256, 0, s>>>(g.pd, g.st);
-    DMP_CHECK(launch_split_grouped_rowmax(g.splitX, g.count, g.units_rowmax, g.st, s));
+    // the row maxima of X2 come from the square's epilogue
     DMP_CHECK(launch_split_grouped_digits(g.splitX, g.count, g.units_digits, g.S, g.kind, g.st, s));
     if (trs4) {
         DMP_CHECK(launch_split_grouped_rowmax(g.splitT[par], g.count, g.units_rowmax, g.st, s));

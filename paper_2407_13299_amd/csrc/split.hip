@@ -192,7 +192,10 @@ __global__ __launch_bounds__(256) void k_digits(const SplitDesc* descs, int coun
     const int r = rb * kFragRows + (lane & 31);
     const int k0 = kc * CK + (lane >> 5) * NE;
     const int e = exponent_of(d.maxbits[r]);
-    if (kc == 0 && lane < 32) d.expo[r] = e;
+    if (kc == 0 && lane < 32) {
+        d.expo[r] = e;
+        if (d.clear != nullptr) d.clear[r] = 0;
+    }
 
     double v[NE];
     if (r < d.R) {
