@@ -38,7 +38,8 @@ def parse():
     ap.add_argument("--slices", type=int, default=None,
                     help="slices (default 7; batched_64: 0 = the tuned table)")
     ap.add_argument("--kind", default="int8", choices=["int8", "fp16"])
-    ap.add_argument("--workload", default="tb_8192")
+    ap.add_argument("--workload", default="tb_8192",
+                    choices=["tb_8192", "batched_64", "adjoint_2048", "small_spectrum", "slice_sweep"])
     ap.add_argument("--native-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-native", action="store_true")
@@ -141,6 +142,85 @@ def bench_batched(a):
     print(json.dumps(line), flush=True)
 
 
+def bench_small(a):
+    """n = 256 spectrum-controlled H, plain canonical purification with FP64
+    (rocBLAS) products beside the INT8 Ozaki products; the reference is the
+    construction itself (P = Q_occ Q_occ^T, E = sum of the occupied levels)."""
+    import torch
+    import paper_2407_13299_amd as dmp
+    from paper_2407_13299_amd.workloads import spectrum_hamiltonian
+
+    h, q, lam = spectrum_hamiltonian(256, 128, seed=0)
+    p_exact = q[:, :128] @ q[:, :128].T
+    e_exact = float(lam[:128].sum())
+    H = torch.from_numpy(h).cuda()
+    legs = {}
+    for name, kw in (("fp64", dict(kind="native")), ("int8_s7", dict(kind="int8", slices=7))):
+        dmp.purify(H, 128, tol=1e-12, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            p, e, info = dmp.purify(H, 128, tol=1e-12, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / a.steps * 1e3
+        legs[name] = dict(ms=ms, iters=info["iters"], stop=info["stop"],
+                          max_dP=float(np.max(np.abs(p.cpu().numpy() - p_exact))),
+                          dE=abs(e - e_exact),
+                          tflops_fp64_equiv=info["iters"] * 4.0 * 256 ** 3 / (ms / 1e3) / 1e12)
+    line = {"metric": "small purification time (n=256, spectrum-controlled, tol 1e-12)",
+            "value": legs["fp64"]["ms"], "unit": "ms", "n_gpus": 1, "steps": a.steps,
+            "warmup": 1, "ms_per_step": legs["fp64"]["ms"], "higher_is_better": False,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "small_spectrum", "n": 256, "nocc": 128}, "legs": legs}
+    print(json.dumps(line), flush=True)
+
+
+def bench_sweep(a):
+    """n = 2048 tight-binding purification against the slice count, INT8 and
+    FP16 slices: time, iterations and errors against a 12-slice run (an
+    FP64-level reference), plus the FP64 (rocBLAS) run."""
+    import torch
+    import paper_2407_13299_amd as dmp
+    from paper_2407_13299_amd.workloads import workload
+
+    w = workload("tb_2048")
+    H = torch.from_numpy(w["H"]).cuda()
+    nocc, tol = w["nocc"], w["tol"]
+    p_ref, e_ref, _ = dmp.purify(H, nocc, tol=tol, slices=12)
+    rows = []
+    for kind in ("int8", "fp16"):
+        for s in range(2, 9):
+            dmp.purify(H, nocc, tol=tol, slices=s, kind=kind)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p, e, info = dmp.purify(H, nocc, tol=tol, slices=s, kind=kind)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            dp = float(torch.max(torch.abs(p - p_ref)).item())
+            de = abs(e - e_ref)
+            rows.append(dict(kind=kind, slices=s, ms=ms, iters=info["iters"], stop=info["stop"],
+                             max_dP=dp if np.isfinite(dp) else None,     # JSON has no NaN
+                             dE=de if np.isfinite(de) else None))
+            print(f"# {kind} S={s}: {ms:.1f} ms {info['iters']} iterations {info['stop']}",
+                  file=sys.stderr, flush=True)
+    dmp.purify(H, nocc, tol=tol, kind="native")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p, e, info = dmp.purify(H, nocc, tol=tol, kind="native")
+    torch.cuda.synchronize()
+    native = dict(ms=(time.perf_counter() - t0) * 1e3, iters=info["iters"],
+                  max_dP=float(torch.max(torch.abs(p - p_ref)).item()), dE=abs(e - e_ref))
+    s7 = next(r for r in rows if r["kind"] == "int8" and r["slices"] == 7)
+    line = {"metric": "slice sweep: purification time and error against S (n=2048 tight binding)",
+            "value": s7["ms"], "unit": "ms (INT8, S=7)", "n_gpus": 1, "steps": 1, "warmup": 1,
+            "ms_per_step": s7["ms"], "higher_is_better": False, "scaling": "weak",
+            "vs_baseline": None, "dtype": "i8", "data": "synthetic",
+            "config": {"workload": "slice_sweep", "n": 2048, "nocc": nocc, "tol": tol,
+                       "reference": "12-slice run"},
+            "sweep": rows, "native_fp64": native}
+    print(json.dumps(line), flush=True)
+
+
 def bench_adjoint(a):
     """dL/dH for L = tr(P W) on the n = 2048 tight-binding workload: taped
     forward purification plus the checkpointed reverse pass."""
@@ -197,6 +277,12 @@ def main():
         return
     if a.workload == "adjoint_2048":
         bench_adjoint(a)
+        return
+    if a.workload == "small_spectrum":
+        bench_small(a)
+        return
+    if a.workload == "slice_sweep":
+        bench_sweep(a)
         return
     import torch
     import paper_2407_13299_amd as dmp
