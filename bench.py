@@ -39,7 +39,8 @@ def parse():
                     help="slices (default 7; batched_64: 0 = the tuned table)")
     ap.add_argument("--kind", default="int8", choices=["int8", "fp16"])
     ap.add_argument("--workload", default="tb_8192",
-                    choices=["tb_8192", "batched_64", "adjoint_2048", "small_spectrum", "slice_sweep"])
+                    choices=["tb_8192", "batched_64", "adjoint_2048", "small_spectrum", "slice_sweep",
+                             "gemm_8192"])
     ap.add_argument("--native-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-native", action="store_true")
@@ -221,6 +222,42 @@ def bench_sweep(a):
     print(json.dumps(line), flush=True)
 
 
+def bench_gemm(a):
+    """C = A B at n = 8192 (N(0,1) entries, seeded) through dmp_ozaki_gemm
+    (INT8, S slices, full tiles; A split by rows, B by columns) against rocBLAS
+    DGEMM; FP64-equivalent TFLOP/s = 2 n^3 / time."""
+    import torch
+    import paper_2407_13299_amd as dmp
+
+    n = 8192
+    g = torch.Generator().manual_seed(5)
+    A = torch.randn(n, n, generator=g, dtype=torch.float64).cuda()
+    B = torch.randn(n, n, generator=g, dtype=torch.float64).cuda()
+    out = {}
+    for name, kw in (("ozaki", dict(slices=a.slices, kind=a.kind)), ("native", dict(kind="native"))):
+        C = dmp.ozaki_gemm(A, B, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            C = dmp.ozaki_gemm(A, B, out=C, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / a.steps * 1e3
+        out[name] = (ms, C)
+    ms, C = out["ozaki"]
+    msn, Cn = out["native"]
+    rel = float(torch.max(torch.abs(C - Cn)).item() / torch.max(torch.abs(Cn)).item())
+    line = {"metric": "Ozaki GEMM time & FP64-equiv TFLOP/s (n=8192, C = A B)",
+            "value": 2.0 * n ** 3 / (ms / 1e3) / 1e12, "unit": "TFLOP/s (FP64-equivalent)",
+            "n_gpus": 1, "steps": a.steps, "warmup": 1, "ms_per_step": ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "i8" if a.kind == "int8" else "f16", "data": "synthetic",
+            "config": {"workload": "gemm_8192", "n": n, "slices": a.slices, "kind": a.kind},
+            "native_fp64": {"ms": msn, "tflops": 2.0 * n ** 3 / (msn / 1e3) / 1e12,
+                            "speedup_ozaki_vs_native": msn / ms},
+            "max_rel_diff_vs_native": rel}
+    print(json.dumps(line), flush=True)
+
+
 def bench_adjoint(a):
     """dL/dH for L = tr(P W) on the n = 2048 tight-binding workload: taped
     forward purification plus the checkpointed reverse pass."""
@@ -283,6 +320,9 @@ def main():
         return
     if a.workload == "slice_sweep":
         bench_sweep(a)
+        return
+    if a.workload == "gemm_8192":
+        bench_gemm(a)
         return
     import torch
     import paper_2407_13299_amd as dmp
