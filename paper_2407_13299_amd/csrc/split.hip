@@ -50,9 +50,13 @@ __device__ inline bool skipped(const SplitDesc& d, const DevState* st) {
 // Entry (r, k) of the combined operand ta A + tb A2 + tc I.  Written with
 // explicit fused multiply-adds so that the row-max and the digit kernels
 // compute the same value bit for bit.
+__device__ inline double combine(double ta, double tb, double tc, double a, double a2, bool diag) {
+    return __builtin_fma(ta, a, __builtin_fma(tb, a2, diag ? tc : 0.0));
+}
+
 __device__ inline double combined(const SplitDesc& d, const DevState& s, int r, int k) {
     const int64_t ij = int64_t(r) * d.lda + k;
-    return __builtin_fma(s.ta, d.A[ij], __builtin_fma(s.tb, d.A2[ij], r == k ? s.tc : 0.0));
+    return combine(s.ta, s.tb, s.tc, d.A[ij], d.A2[ij], r == k);
 }
 
 // Magnitudes are compared as the bit patterns of |x|: for non-negative
@@ -171,9 +175,16 @@ __device__ inline int exponent_of(uint64_t bits) {
     return e;
 }
 
-// Digits: one wavefront per fragment block (32 operand rows x CK reduction
-// elements); lane l owns operand row l % 32 and NE = CK / 2 consecutive
-// reduction elements.  A workgroup of 256 threads handles 4 blocks.
+// Digits: a workgroup of 4 wavefronts owns one 32-row block of the operand
+// and 4 consecutive chunks of CK reduction elements (W = 4 CK); wave w turns
+// chunk 4 q + w into its fragment block, where lane l owns operand row l % 32
+// and NE = CK / 2 consecutive reduction elements (the MFMA operand layout).
+// Operand rows that are matrix rows (trans == 0, also the combined operand)
+// are first staged through LDS: the workgroup reads the 32 x W panel row by
+// row, each wave 64 consecutive doubles per load, so the HBM reads are
+// coalesced although every lane then needs a piece of its own row.  Columns
+// (trans == 1) are read directly: there consecutive lanes own consecutive
+// rows, which are adjacent in memory.
 // HALVES (Markidis kind, S = 2, FP16): instead of digits, the high and low
 // FP16 parts of x = a 2^-e (|x| < 1): X0 = FP16[x], X1 = FP16[x - X0].
 template <int S, bool FP16, bool HALVES = false>
@@ -181,40 +192,84 @@ __global__ __launch_bounds__(256) void k_digits(const SplitDesc* descs, int coun
                                                 SplitDesc one, const DevState* st) {
     constexpr int CK = FP16 ? 16 : 32;
     constexpr int NE = CK / 2;
+    constexpr int W = 4 * CK;
+    constexpr int LDW = W + 2;   // row stride in doubles: rows start 4 banks apart
+    constexpr int PER = kFragRows * W / 256;
+    __shared__ double panel[kFragRows * LDW];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int local;
-    const SplitDesc& d = pick<false>(descs, count, one, blockIdx.x, &local);
+    // a copy: held in scalar registers, so that the LDS stores below cannot
+    // alias it and force its fields to be reloaded
+    const SplitDesc d = pick<false>(descs, count, one, blockIdx.x, &local);
     if (skipped(d, st)) return;
     const int rb_count = int(round_up(d.R, kPad)) / kFragRows;
-    const int blk = local * 4 + wave;
-    if (blk >= rb_count * d.KC) return;
-    const int rb = blk / d.KC, kc = blk % d.KC;
+    const int kq_count = (d.KC + 3) / 4;
+    if (local >= rb_count * kq_count) return;
+    const int rb = local / kq_count, kq = local % kq_count;
+    const int kc = kq * 4 + wave;
     const int r = rb * kFragRows + (lane & 31);
     const int k0 = kc * CK + (lane >> 5) * NE;
     const int e = exponent_of(d.maxbits[r]);
-    if (kc == 0 && lane < 32) {
+    if (kq == 0 && wave == 0 && lane < 32) {
         d.expo[r] = e;
         if (d.clear != nullptr) d.clear[r] = 0;
     }
 
     double v[NE];
-    if (r < d.R) {
+    if (!d.trans) {
+        // every wave takes part in the staging and the barrier
+        // all loads are issued before the first LDS write, so PER of them
+        // are in flight per lane
+        const int kb = kq * W;
+        double stage[PER];
         if (d.A2 != nullptr) {
+            double stage2[PER];
+#pragma unroll
+            for (int t = 0; t < PER; ++t) {
+                const int q = threadIdx.x + 256 * t, rr = q / W, cc = q % W;
+                const int row = rb * kFragRows + rr, k = kb + cc;
+                const bool in = row < d.R && k < d.K;
+                stage[t] = in ? d.A[int64_t(row) * d.lda + k] : 0.0;
+                stage2[t] = in ? d.A2[int64_t(row) * d.lda + k] : 0.0;
+            }
             const DevState& s = st[d.state_index];
+            const double ta = s.ta, tb = s.tb, tc = s.tc;
 #pragma unroll
-            for (int i = 0; i < NE; ++i) v[i] = (k0 + i < d.K) ? combined(d, s, r, k0 + i) : 0.0;
-        } else if (!d.trans) {
-            const double* src = d.A + int64_t(r) * d.lda;
-#pragma unroll
-            for (int i = 0; i < NE; ++i) v[i] = (k0 + i < d.K) ? src[k0 + i] : 0.0;
+            for (int t = 0; t < PER; ++t) {
+                const int q = threadIdx.x + 256 * t, rr = q / W, cc = q % W;
+                const int row = rb * kFragRows + rr, k = kb + cc;
+                stage[t] = (row < d.R && k < d.K)
+                               ? combine(ta, tb, tc, stage[t], stage2[t], row == k)
+                               : 0.0;
+            }
         } else {
+#pragma unroll
+            for (int t = 0; t < PER; ++t) {
+                const int q = threadIdx.x + 256 * t, rr = q / W, cc = q % W;
+                const int row = rb * kFragRows + rr, k = kb + cc;
+                stage[t] = (row < d.R && k < d.K) ? d.A[int64_t(row) * d.lda + k] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+            const int q = threadIdx.x + 256 * t;
+            panel[(q / W) * LDW + q % W] = stage[t];
+        }
+        __syncthreads();
+        if (kc >= d.KC) return;
+        const double* src = panel + (lane & 31) * LDW + wave * CK + (lane >> 5) * NE;
+#pragma unroll
+        for (int i = 0; i < NE; ++i) v[i] = src[i];
+    } else {
+        if (kc >= d.KC) return;
+        if (r < d.R) {
 #pragma unroll
             for (int i = 0; i < NE; ++i)
                 v[i] = (k0 + i < d.K) ? d.A[int64_t(k0 + i) * d.lda + r] : 0.0;
-        }
-    } else {
+        } else {
 #pragma unroll
-        for (int i = 0; i < NE; ++i) v[i] = 0.0;
+            for (int i = 0; i < NE; ++i) v[i] = 0.0;
+        }
     }
 
     uint8_t* base = d.planes + (int64_t(rb) * d.KC + kc) * int64_t(S) * kFragBytes + lane * 16;
@@ -293,7 +348,7 @@ static const DigitsFn kDigits[kMaxSlices + 1] = {
 // Units per matrix of each split kernel.
 int split_units_rowmax(int R) { return int(round_up(R, kPad)) / 4; }
 int split_units_colmax(int R, int K) { return ((R + 63) / 64) * ((K + 255) / 256); }
-int split_units_digits(int R, int KC) { return (int(round_up(R, kPad)) / kFragRows * KC + 3) / 4; }
+int split_units_digits(int R, int KC) { return int(round_up(R, kPad)) / kFragRows * ((KC + 3) / 4); }
 
 // Split one operand.  ``d`` describes it; ``st`` (nullable) skips the work
 // once the state's done flag is set.
