@@ -33,14 +33,14 @@ FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 (vector and matrix)
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--slices", type=int, default=None,
                     help="slices (default 7; batched_64: 0 = the tuned table)")
     ap.add_argument("--kind", default="int8", choices=["int8", "fp16"])
     ap.add_argument("--workload", default="tb_8192",
                     choices=["tb_8192", "batched_64", "adjoint_2048", "small_spectrum", "slice_sweep",
-                             "gemm_8192"])
+                             "gemm_8192", "slices_8192"])
     ap.add_argument("--native-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-native", action="store_true")
@@ -222,6 +222,58 @@ def bench_sweep(a):
     print(json.dumps(line), flush=True)
 
 
+def tb8192_accuracy(p, e):
+    """max |dP| over the stored oracle samples (entries and whole rows of the
+    n = 8192 tight-binding projector) and |dE|; {} if the samples are absent."""
+    import torch
+    gpath = os.path.join(ROOT, "tests", "golden", "tb8192_reference.npz")
+    if not os.path.exists(gpath):
+        return {}
+    ref = np.load(gpath)
+    samp = p[torch.from_numpy(ref["si"]).cuda(), torch.from_numpy(ref["sj"]).cuda()].cpu().numpy()
+    rows = p[torch.from_numpy(ref["rows"]).cuda()].cpu().numpy()
+    dp = float(max(np.max(np.abs(samp - ref["P_samples"])), np.max(np.abs(rows - ref["P_rows"]))))
+    de = float(abs(e - float(ref["E"])))
+    return dict(max_dP_sampled=dp if np.isfinite(dp) else None,     # JSON has no NaN
+                dE=de if np.isfinite(de) else None)
+
+
+def bench_slices8192(a):
+    """n = 8192 tight-binding canonical purification against the slice count:
+    INT8 with S = 6, 7, 8 and FP16 with S = 7 (one warm-up and one timed run
+    each), time, iterations and accuracy against the stored oracle samples."""
+    import torch
+    import paper_2407_13299_amd as dmp
+    from paper_2407_13299_amd.workloads import workload
+
+    w = workload("tb_8192")
+    H = torch.from_numpy(w["H"]).cuda()
+    n, nocc, tol = w["H"].shape[0], w["nocc"], w["tol"]
+    P = torch.empty_like(H)
+    rows = []
+    for kind, s in (("int8", 6), ("int8", 7), ("int8", 8), ("fp16", 7)):
+        dmp.purify(H, nocc, tol=tol, slices=s, kind=kind, out=P, max_iter=a.max_iter)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, e, info = dmp.purify(H, nocc, tol=tol, slices=s, kind=kind, out=P, max_iter=a.max_iter)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        rows.append(dict(kind=kind, slices=s, ms=ms, iters=info["iters"], stop=info["stop"],
+                         tflops_fp64_equiv=info["iters"] * 4.0 * n ** 3 / (ms / 1e3) / 1e12,
+                         **tb8192_accuracy(P, e)))
+        print(f"# {kind} S={s}: {ms:.1f} ms {info['iters']} iterations {info['stop']}",
+              file=sys.stderr, flush=True)
+    s7 = rows[1]
+    line = {"metric": "purification time and error against S (n=8192 tight binding)",
+            "value": s7["ms"], "unit": "ms (INT8, S=7)", "n_gpus": 1, "steps": 1, "warmup": 1,
+            "ms_per_step": s7["ms"], "higher_is_better": False, "scaling": "weak",
+            "vs_baseline": None, "dtype": "i8", "data": "synthetic",
+            "config": {"workload": "slices_8192", "n": n, "nocc": nocc, "tol": tol,
+                       "reference": "oracle samples (eigendecomposition projector)"},
+            "sweep": rows}
+    print(json.dumps(line), flush=True)
+
+
 def bench_gemm(a):
     """C = A B at n = 8192 (N(0,1) entries, seeded) through dmp_ozaki_gemm
     (INT8, S slices, full tiles; A split by rows, B by columns) against rocBLAS
@@ -324,6 +376,9 @@ def main():
     if a.workload == "gemm_8192":
         bench_gemm(a)
         return
+    if a.workload == "slices_8192":
+        bench_slices8192(a)
+        return
     import torch
     import paper_2407_13299_amd as dmp
     from paper_2407_13299_amd import _lib
@@ -344,15 +399,7 @@ def main():
                           max_iter=a.max_iter, method=method, triangle=triangle)
 
     def accuracy(p, e):
-        gpath = os.path.join(ROOT, "tests", "golden", "tb8192_reference.npz")
-        if a.workload != "tb_8192" or not os.path.exists(gpath):
-            return {}
-        ref = np.load(gpath)
-        samp = p[torch.from_numpy(ref["si"]).cuda(), torch.from_numpy(ref["sj"]).cuda()].cpu().numpy()
-        rows = p[torch.from_numpy(ref["rows"]).cuda()].cpu().numpy()
-        return dict(max_dP_sampled=float(max(np.max(np.abs(samp - ref["P_samples"])),
-                                             np.max(np.abs(rows - ref["P_rows"])))),
-                    dE=float(abs(e - float(ref["E"]))))
+        return tb8192_accuracy(p, e) if a.workload == "tb_8192" else {}
 
     if a.calibrate_copy:
         src = torch.empty(a.calibrate_copy << 20, dtype=torch.uint8, device="cuda").fill_(1)
@@ -489,6 +536,7 @@ def main():
         "steps": a.steps,
         "warmup": a.warmup,
         "ms_per_step": ms_per_step,
+        "ms_median": float(np.median(times)) * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
