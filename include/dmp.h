@@ -149,8 +149,11 @@ int dmp_ozaki_gemm(char transA, char transB, int m, int n, int k,
  * same slices and kind.  The row splits of all A_b and the slice GEMM of all
  * products are one grouped launch each; the column split of every B_b is a
  * launch of its own.  m, n, k and the pointer arrays are HOST arrays of
- * length count; the matrices are on the device.  Blocks until the launches
- * have been queued and their host-side descriptors copied. */
+ * length count; the matrices are on the device.  Returns 0 from the
+ * workspace query for a null array or a size below 1.  Synchronises the
+ * stream once, after copying the per-product descriptors into the workspace
+ * (so work queued on the stream before the call is waited for); the splits
+ * and the product are then queued asynchronously, like dmp_ozaki_gemm. */
 size_t dmp_gemm_batched_workspace_bytes(int count, const int* m, const int* n,
                                         const int* k, int slices, dmp_kind kind);
 int dmp_ozaki_gemm_batched(int count, const int* m, const int* n, const int* k,

@@ -43,6 +43,27 @@ def _workspace(nbytes: int, device):
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
 
+def _keep_for(ws: torch.Tensor, stream):
+    """A temporary workspace that asynchronous work on a caller-given stream
+    still reads: tell the caching allocator not to reuse it before that
+    stream has passed this point."""
+    if stream is not None:
+        ws.record_stream(stream)
+
+
+def _check_out(out, shape, like, name="out"):
+    _check_matrix(out, name)
+    if tuple(out.shape) != tuple(shape) or out.device != like.device:
+        raise ValueError(f"{name} must be a {shape[0]}x{shape[1]} tensor on {like.device}")
+
+
+def _square(h, name="H"):
+    _check_matrix(h, name)
+    if h.shape[0] != h.shape[1]:
+        raise ValueError(f"{name} must be square")
+    return h.shape[0]
+
+
 def version() -> str:
     return _lib.load().dmp_version().decode()
 
@@ -65,10 +86,12 @@ def ozaki_gemm(A, B, slices=7, kind="int8", trans_a=False, trans_b=False, out=No
     n = B.shape[0] if trans_b else B.shape[1]
     if k != kb:
         raise ValueError(f"inner dimensions differ: {k} vs {kb}")
+    if A.device != B.device:
+        raise ValueError("A and B are on different devices")
     if out is None:
         out = torch.empty((m, n), dtype=torch.float64, device=A.device)
     else:
-        _check_matrix(out, "out")
+        _check_out(out, (m, n), A)
     kd = _kind(kind)
     ws = _workspace(lib.dmp_gemm_workspace_bytes(m, n, k, slices, kd), A.device)
     st = lib.dmp_ozaki_gemm(b"T" if trans_a else b"N", b"T" if trans_b else b"N", m, n, k,
@@ -76,6 +99,7 @@ def ozaki_gemm(A, B, slices=7, kind="int8", trans_a=False, trans_b=False, out=No
                             _ptr(out), max(1, out.shape[1]), slices, kd, _ptr(ws), ws.numel(),
                             _stream(stream))
     _lib.check(st, "dmp_ozaki_gemm")
+    _keep_for(ws, stream)
     return out
 
 
@@ -85,11 +109,15 @@ def ozaki_gemm_batched(As, Bs, slices=7, kind="int8", stream=None):
     cnt = len(As)
     if len(Bs) != cnt:
         raise ValueError("As and Bs differ in length")
+    if cnt == 0:
+        return []
     for a, b in zip(As, Bs):
         _check_matrix(a, "A")
         _check_matrix(b, "B")
         if a.shape[1] != b.shape[0]:
             raise ValueError("inner dimensions differ")
+        if a.device != As[0].device or b.device != As[0].device:
+            raise ValueError("all matrices must be on one device")
     Cs = [torch.empty((a.shape[0], b.shape[1]), dtype=torch.float64, device=a.device)
           for a, b in zip(As, Bs)]
     IA = ctypes.c_int * cnt
@@ -104,6 +132,7 @@ def ozaki_gemm_batched(As, Bs, slices=7, kind="int8", stream=None):
                                     PA(*[c.data_ptr() for c in Cs]), slices, kd, _ptr(ws),
                                     ws.numel(), _stream(stream))
     _lib.check(st, "dmp_ozaki_gemm_batched")
+    _keep_for(ws, stream)
     return Cs
 
 
@@ -123,14 +152,18 @@ def purify(H, nocc, tol=1e-8, slices=7, kind="int8", max_iter=200, out=None, str
     ``triangle`` (kind 'native'): rocBLAS dsyrk / dsyrkx upper-triangle
     products instead of full DGEMMs."""
     lib = _lib.load()
-    _check_matrix(H, "H")
-    n = H.shape[0]
-    if H.shape[1] != n:
-        raise ValueError("H must be square")
+    n = _square(H)
+    if out is not None:
+        _check_out(out, (n, n), H)
     P = out if out is not None else torch.empty_like(H)
     kd = _kind(kind)
     need = lib.dmp_purify_workspace_bytes(n, slices, kd)
-    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, H.device)
+    ws = workspace
+    if ws is not None and (not isinstance(ws, torch.Tensor) or ws.dtype != torch.uint8
+                           or ws.device != H.device or not ws.is_contiguous()):
+        raise TypeError("workspace must be a contiguous uint8 tensor on the device of H")
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, H.device)
     e = ctypes.c_double(0.0)
     info = _lib.DmpInfo()
     flags = (_lib.REFINE_MCWEENY if refine else 0) | (_lib.NATIVE_TRIANGLE if triangle else 0)
@@ -148,8 +181,14 @@ def purify_batched(Hs, noccs, tol=1e-8, slices=0, kind="int8", max_iter=200, str
     Returns (list of P, list of E, list of info dicts)."""
     lib = _lib.load()
     cnt = len(Hs)
+    if len(noccs) != cnt:
+        raise ValueError("Hs and noccs differ in length")
+    if cnt == 0:
+        return [], [], []
     for h in Hs:
-        _check_matrix(h, "H")
+        _square(h)
+        if h.device != Hs[0].device:
+            raise ValueError("all Hamiltonians must be on one device")
     Ps = [torch.empty_like(h) for h in Hs]
     IA = ctypes.c_int * cnt
     PA = ctypes.c_void_p * cnt
@@ -178,8 +217,7 @@ class PurifyTape:
     def __init__(self, H, nocc, tol=1e-8, slices=7, kind="int8", max_iter=200, stride=0,
                  stream=None):
         lib = _lib.load()
-        _check_matrix(H, "H")
-        n = H.shape[0]
+        n = _square(H)
         self.n = n
         self.device = H.device
         self.H = H          # the library copies H, this only keeps the caller's alive
@@ -213,7 +251,7 @@ class PurifyTape:
 
     def backward(self, Pbar, stream=None):
         lib = _lib.load()
-        _check_matrix(Pbar, "Pbar")
+        _check_out(Pbar, (self.n, self.n), self.P, "Pbar")
         Pbar = 0.5 * (Pbar + Pbar.T)
         Pbar = Pbar.contiguous()
         Hbar = torch.empty_like(Pbar)

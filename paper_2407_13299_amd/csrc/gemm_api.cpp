@@ -155,6 +155,9 @@ size_t dmp_gemm_batched_workspace_bytes(int count, const int* m, const int* n, c
                                         int slices, dmp_kind kind) {
     if (count < 0 || slices < 1 || slices > kMaxSlices) return 0;
     if (kind == DMP_MARKIDIS_FP16 && slices > kMaxTerms) return 0;
+    if (count > 0 && (!m || !n || !k)) return 0;
+    for (int b = 0; b < count; ++b)
+        if (m[b] < 1 || n[b] < 1 || k[b] < 1) return 0;
     Carver c(nullptr);
     size_t tiles = 0;
     for (int b = 0; b < count; ++b) {
@@ -264,6 +267,9 @@ int dmp_ozaki_gemm_batched(int count, const int* m, const int* n, const int* k,
     DMP_CHECK_HIP(hipMemcpyAsync(sd_dev, sa.data(), count * sizeof(SplitDesc), hipMemcpyHostToDevice, s));
     DMP_CHECK_HIP(hipMemcpyAsync(md_dev, md.data(), count * sizeof(MatDesc), hipMemcpyHostToDevice, s));
     DMP_CHECK_HIP(hipMemcpyAsync(t_dev, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, s));
+    // the host vectors must outlive the asynchronous copies; the launches
+    // below stay asynchronous
+    DMP_CHECK_HIP(hipStreamSynchronize(s));
     // A: one grouped row split; B: column splits (per product, small count)
     DMP_CHECK(launch_split_grouped_rowmax(sd_dev, count, ur_a, nullptr, s));
     DMP_CHECK(launch_split_grouped_digits(sd_dev, count, ud_a, slices, kind, nullptr, s));
@@ -277,8 +283,6 @@ int dmp_ozaki_gemm_batched(int count, const int* m, const int* n, const int* k,
     p.mode = EPI_STORE;
     p.spread = count > 1 ? 1 : 0;
     DMP_CHECK(launch_ozgemm(slices, kind, p, int(tiles.size()), s));
-    // the host vectors must outlive the asynchronous copies
-    DMP_CHECK_HIP(hipStreamSynchronize(s));
     return DMP_OK;
 }
 

@@ -1,0 +1,70 @@
+"""Argument checks of the Python binding and asynchronous GEMMs on a side
+stream (C ABI through the binding)."""
+import numpy as np
+import pytest
+
+from oracle import ozaki
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+dmp = pytest.importorskip("paper_2407_13299_amd")
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def test_gemm_rejects_a_wrong_output_shape():
+    a, b = dev(np.ones((40, 30))), dev(np.ones((30, 20)))
+    with pytest.raises(ValueError):
+        dmp.ozaki_gemm(a, b, slices=3, out=torch.empty((20, 40), dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        dmp.ozaki_gemm(a, b, slices=3, out=torch.empty((39, 20), dtype=torch.float64, device="cuda"))
+
+
+def test_purify_rejects_bad_arguments():
+    h = dev(np.eye(64))
+    with pytest.raises(ValueError):
+        dmp.purify(dev(np.ones((64, 32))), 16)
+    with pytest.raises(ValueError):
+        dmp.purify(h, 16, out=torch.empty((32, 64), dtype=torch.float64, device="cuda"))
+    with pytest.raises(TypeError):
+        dmp.purify(h, 16, workspace=torch.empty(1 << 20, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        dmp.purify_batched([h], [16, 16])
+    assert dmp.purify_batched([], []) == ([], [], [])
+    assert dmp.ozaki_gemm_batched([], []) == []
+
+
+def test_purify_uses_a_caller_workspace():
+    from paper_2407_13299_amd.workloads import spectrum_hamiltonian
+    h, _, _ = spectrum_hamiltonian(130, 65, seed=5)
+    hd = dev(h)
+    p0, e0, _ = dmp.purify(hd, 65, tol=1e-10, slices=7)
+    ws = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    p1, e1, _ = dmp.purify(hd, 65, tol=1e-10, slices=7, workspace=ws)
+    torch.cuda.synchronize()
+    assert torch.equal(p0, p1) and e0 == e1
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_gemm_on_a_side_stream(batched):
+    """The product is queued on a non-current stream and its temporary
+    workspace is held for that stream; the current stream allocates and
+    overwrites memory meanwhile.  The result equals the oracle's bit for bit."""
+    rng = np.random.default_rng(11)
+    a, b = rng.standard_normal((300, 257)), rng.standard_normal((257, 190))
+    ref = ozaki.ozaki_gemm(a, b, 6)
+    ad, bd = dev(a), dev(b)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    if batched:
+        c = dmp.ozaki_gemm_batched([ad], [bd], slices=6, stream=side)[0]
+    else:
+        c = dmp.ozaki_gemm(ad, bd, slices=6, stream=side)
+    junk = [torch.full((1 << 22,), 7.0, dtype=torch.float64, device="cuda") for _ in range(8)]
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    del junk
+    assert np.array_equal(c.cpu().numpy(), ref)
