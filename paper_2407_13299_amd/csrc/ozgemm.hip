@@ -246,26 +246,59 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
     double s0 = 0.0, s1 = 0.0;
     // row maxima of the output for the next split (purification modes):
     // bit patterns of |value| (their integer order is the numeric order, a
-    // NaN above an infinity), per element of this lane (row) and per column
-    uint64_t rmax[16];
+    // NaN above an infinity); per element reduced over the 32 lanes of a
+    // half-wavefront (the lanes of one row), and per column over the lane's
+    // elements (the mirror's rows)
+    const bool rowmax = mode != EPI_STORE && d.rowmax != nullptr;
+    uint64_t mine = 0;
     uint64_t cmax = 0;
-#pragma unroll
-    for (int v = 0; v < 16; ++v) rmax[v] = 0;
     auto absbits = [](double x) __attribute__((always_inline)) {
         return static_cast<uint64_t>(__double_as_longlong(x)) & 0x7fffffffffffffffull;
     };
+    // The epilogue runs in three phases: the group sums of all 16 elements
+    // of the lane are combined first (the accumulators are then dead), then
+    // every load of the epilogue is issued, then the outputs are formed and
+    // stored.  The compiler cannot tell that the output does not alias P,
+    // X2, H or the exponents, so a load placed after a store would wait for
+    // it and every element would pay a full memory latency.
+    double hsum[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        if constexpr (TERMS > 0) {
+            hsum[v] = double(accf[v]);
+        } else {
+            double h = double(acc[S - 1][v]);
+#pragma unroll
+            for (int g = S - 2; g >= 0; --g) h = h * 0x1p-8 + double(acc[g][v]);
+            hsum[v] = h;
+        }
+    }
+    // Materialise the combined sums here (an empty asm statement that takes
+    // each as a register operand): otherwise the combination is sunk to its
+    // uses below, past the loads, and the accumulators stay live beside them.
+#pragma unroll
+    for (int v = 0; v < 16; ++v) asm volatile("" : "+v"(hsum[v]));
+    int eiv[16];
+    double pv[16], xv[16], hv[16];
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         const int row = row0 + (v >> 2) * 8 + (v & 3);
-        double h;
-        if constexpr (TERMS > 0) {
-            h = double(accf[v]);
-        } else {
-            h = double(acc[S - 1][v]);
-#pragma unroll
-            for (int g = S - 2; g >= 0; --g) h = h * 0x1p-8 + double(acc[g][v]);
+        eiv[v] = d.ea[row];
+        pv[v] = xv[v] = hv[v] = 0.0;
+        if (mode != EPI_STORE && row < n && col < n && row <= col) {
+            const int64_t ij = int64_t(row) * n + col;
+            pv[v] = d.P[ij];
+            if (mode == EPI_UPDATE) {
+                xv[v] = d.X2[ij];
+                hv[v] = d.H[ij];
+            }
         }
-        const int ei = d.ea[row];
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int row = row0 + (v >> 2) * 8 + (v & 3);
+        const double h = hsum[v];
+        const int ei = eiv[v];
         constexpr int shift = TERMS > 0 ? 0 : 2 * kTopBits;
         const double c = no_product ? 0.0
                          : (ei >= kNonFiniteExp || fj >= kNonFiniteExp)
@@ -275,47 +308,45 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
             if (row < d.M && col < d.N) d.out[int64_t(row) * d.ldc + col] = c;
             continue;
         }
-        if (row >= n || col >= n || row > col) continue;
-        const bool diag = (row == col);
-        const double mult = diag ? 1.0 : 2.0;
-        const int64_t ij = int64_t(row) * n + col, ji = int64_t(col) * n + row;
-        const double pij = d.P[ij];
-        double w;
-        if (mode == EPI_SQUARE) {
-            w = c;
-            if (diag) s0 += pij - c;
-            s1 += mult * c * ((diag ? 1.0 : 0.0) - pij);
-        } else if (mode == EPI_SQUARE_TRS4) {
-            // tr F = sum_ij X2_ij (4 X_ij - 3 X2_ij), tr G = sum_ij (X_ij - X2_ij)^2
-            w = c;
-            const double r = pij - c;
-            s0 += mult * c * (4.0 * pij - 3.0 * c);
-            s1 += mult * r * r;
-        } else {  // EPI_UPDATE
-            w = alpha * pij + beta * d.X2[ij] + gamma * c;
-            s0 += mult * w * d.H[ij];
-            if (diag) s1 += w;
+        uint64_t bits = 0;
+        if (row < n && col < n && row <= col) {
+            const bool diag = (row == col);
+            const double mult = diag ? 1.0 : 2.0;
+            const int64_t ij = int64_t(row) * n + col, ji = int64_t(col) * n + row;
+            const double pij = pv[v];
+            double w;
+            if (mode == EPI_SQUARE) {
+                w = c;
+                if (diag) s0 += pij - c;
+                s1 += mult * c * ((diag ? 1.0 : 0.0) - pij);
+            } else if (mode == EPI_SQUARE_TRS4) {
+                // tr F = sum_ij X2_ij (4 X_ij - 3 X2_ij), tr G = sum_ij (X_ij - X2_ij)^2
+                w = c;
+                const double r = pij - c;
+                s0 += mult * c * (4.0 * pij - 3.0 * c);
+                s1 += mult * r * r;
+            } else {  // EPI_UPDATE
+                w = alpha * pij + beta * xv[v] + gamma * c;
+                s0 += mult * w * hv[v];
+                if (diag) s1 += w;
+            }
+            d.out[ij] = w;
+            if (!diag) d.out[ji] = w;
+            bits = absbits(w);
+            cmax = bits > cmax ? bits : cmax;      // its mirror (col, row) of row ``col``
         }
-        d.out[ij] = w;
-        if (!diag) d.out[ji] = w;
-        const uint64_t b = absbits(w);
-        rmax[v] = b;                       // element (row, col) of row ``row``
-        cmax = b > cmax ? b : cmax;        // its mirror (col, row) of row ``col``
-    }
-    if (mode != EPI_STORE && d.rowmax != nullptr) {
-        // rows: the 32 lanes of a half share the 16 rows of their v values
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
+        if (rowmax) {
+            // element (row, col) of row ``row``: max over the half's 32 columns
 #pragma unroll
             for (int off = 1; off < 32; off <<= 1) {
-                const uint64_t o = static_cast<uint64_t>(__shfl_xor(static_cast<long long>(rmax[v]), off, 64));
-                rmax[v] = o > rmax[v] ? o : rmax[v];
+                const uint64_t o = static_cast<uint64_t>(__shfl_xor(static_cast<long long>(bits), off, 64));
+                bits = o > bits ? o : bits;
             }
+            if ((lane & 31) == v) mine = bits;
         }
+    }
+    if (rowmax) {
         const int myv = lane & 31;
-        uint64_t mine = 0;
-#pragma unroll
-        for (int v = 0; v < 16; ++v) mine = (myv == v) ? rmax[v] : mine;
         const int myrow = row0 + (myv >> 2) * 8 + (myv & 3);
         if (myv < 16 && myrow < n && mine != 0)
             atomicMax(reinterpret_cast<unsigned long long*>(d.rowmax) + myrow,
