@@ -177,16 +177,21 @@ __global__ __launch_bounds__(256) void k_init_p0(const PurDesc* pd, const DevSta
     __shared__ double sh[4];
     const PurDesc& d = pd[blockIdx.y];
     const DevState& s = states[blockIdx.y];
+    // locals: the stores to P below could alias the descriptor and the state
+    // as far as the compiler knows, and would force them to be reloaded
     const int n = d.n;
+    const double* H = d.H;
+    double* P = d.Pb[0];
+    const double lam = s.lambda, mu = s.mu, theta = s.theta;
     const int64_t tot = int64_t(n) * n;
     double e = 0.0;
     if (!s.nonfinite) {
         for (int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x; idx < tot;
              idx += int64_t(kE0Blocks) * 256) {
             const int i = int(idx / n), j = int(idx % n);
-            const double h = i <= j ? d.H[idx] : d.H[int64_t(j) * n + i];
-            const double p = s.lambda * ((i == j ? s.mu : 0.0) - h) + (i == j ? s.theta : 0.0);
-            d.Pb[0][idx] = p;
+            const double h = i <= j ? H[idx] : H[int64_t(j) * n + i];
+            const double p = lam * ((i == j ? mu : 0.0) - h) + (i == j ? theta : 0.0);
+            P[idx] = p;
             e += p * h;
         }
     }
@@ -365,6 +370,10 @@ __global__ __launch_bounds__(256) void k_native_update(const PurDesc* pd, const 
     const int2 pr = pairs[blockIdx.x];
     const int I = pr.x, J = pr.y;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    // locals: the stores to Pn could alias the descriptor and the state as
+    // far as the compiler knows, and would force them to be reloaded
+    const double alpha = s.alpha, beta = s.beta, gamma = s.gamma;
+    const double *X2 = d.X2, *X3 = d.X3, *H = d.H;
     double se = 0.0, st = 0.0;
     for (int r = ty; r < 32; r += 8) {
         const int i = I * 32 + r, j = J * 32 + tx;
@@ -372,9 +381,9 @@ __global__ __launch_bounds__(256) void k_native_update(const PurDesc* pd, const 
         if (i < n && j < n && !(I == J && j < i)) {
             const int64_t ij = int64_t(i) * n + j;
             // gamma == 0 (TRS4 without a second product): X3 is not read
-            v = s.alpha * P[ij] + s.beta * d.X2[ij] + (s.gamma != 0.0 ? s.gamma * d.X3[ij] : 0.0);
+            v = alpha * P[ij] + beta * X2[ij] + (gamma != 0.0 ? gamma * X3[ij] : 0.0);
             Pn[ij] = v;
-            se += (i == j ? 1.0 : 2.0) * v * d.H[ij];
+            se += (i == j ? 1.0 : 2.0) * v * H[ij];
             if (i == j) st += v;
         }
         tileT[r][tx] = v;
@@ -418,11 +427,15 @@ __global__ __launch_bounds__(256) void k_native_t(const PurDesc* pd, const DevSt
     if (s.done || s.gamma == 0.0) return;
     const int n = d.n;
     const double* P = d.Pb[s.iters & 1];
+    // locals, as in k_native_update
+    const double ta = s.ta, tb = s.tb, tc = s.tc;
+    const double* X2 = d.X2;
+    double* T = d.T;
     const int64_t tot = int64_t(n) * n;
     for (int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x; idx < tot;
          idx += int64_t(gridDim.x) * 256) {
         const bool diag = idx / n == idx % n;
-        d.T[idx] = s.ta * P[idx] + s.tb * d.X2[idx] + (diag ? s.tc : 0.0);
+        T[idx] = ta * P[idx] + tb * X2[idx] + (diag ? tc : 0.0);
     }
 }
 

@@ -104,9 +104,16 @@ def test_special_occupations_and_errors():
     bad[3, 5] = np.nan
     with pytest.raises(dmp._lib.DmpError, match="ENONFINITE"):
         gpu_purify(bad, 35, slices=7)
-    p1, e1, i1 = gpu_purify(h, 1, slices=7)
-    p_ref, e_ref, _, _ = projector.eigh_projector(h, 1)
-    assert np.max(np.abs(p1 - p_ref)) < TOL_P
+    for nocc in (1, 69):
+        p1, e1, i1 = gpu_purify(h, nocc, slices=7)
+        p_ref, e_ref, _, _ = projector.eigh_projector(h, nocc)
+        assert np.max(np.abs(p1 - p_ref)) < TOL_P and abs(e1 - e_ref) < TOL_E
+    # n = 1: both occupations are the special cases
+    one = np.array([[0.3]])
+    p, e, info = gpu_purify(one, 1, slices=7)
+    assert p.tolist() == [[1.0]] and e == 0.3 and info["iters"] == 0
+    p, e, info = gpu_purify(one, 0, slices=7)
+    assert p.tolist() == [[0.0]] and e == 0.0
 
 
 def test_low_slices_stop_without_convergence():
