@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 INT8_PEAK_TOPS = 5000.0      # MI355X dense INT8 MFMA, TOP/s
 FP16_PEAK_TFLOPS = 2500.0    # MI355X dense FP16 MFMA
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 (vector and matrix)
+NOMINAL_CLOCK_GHZ = 2.4      # the clock the MI355X peaks are quoted at
 
 
 def parse():
@@ -437,6 +438,17 @@ def main():
     ops = [ctypes.c_double(), ctypes.c_double()]
     for i in range(2):
         lib.dmp_timing_read(i, ctypes.byref(ms_k[i]), ctypes.byref(nl[i]), ctypes.byref(ops[i]))
+    # the shader clock inside the GEMMs, from one more (untimed) purification
+    # with the per-workgroup clock counters on
+    clk = [ctypes.c_double(), ctypes.c_double()]
+    lib.dmp_timing_enable(2)
+    lib.dmp_timing_reset()
+    run(a.kind, a.slices, P, ws)
+    torch.cuda.synchronize()
+    for i in range(2):
+        lib.dmp_timing_clock(i, ctypes.byref(clk[i]))
+    lib.dmp_timing_enable(0)
+    lib.dmp_timing_reset()
     ms_per_step = total / a.steps * 1e3
     it = iters[-1]
     fp64_eq = it * 2 * 2.0 * n ** 3
@@ -452,7 +464,8 @@ def main():
             avg_ms = ms_k[i].value / nl[i].value
             per_launch = ops[i].value / nl[i].value
             kernels[name] = dict(avg_ms=avg_ms, launches=nl[i].value,
-                                 tops=per_launch / (avg_ms / 1e3) / 1e12)
+                                 tops=per_launch / (avg_ms / 1e3) / 1e12,
+                                 clock_ghz=clk[i].value)
     dom = kernels.get("update") or kernels.get("square") or {}
     peak = INT8_PEAK_TOPS if a.kind == "int8" else FP16_PEAK_TFLOPS
     achieved = dom.get("tops", 0.0)
@@ -550,6 +563,12 @@ def main():
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "ops": "int8 multiply-adds counted as 2 ops" if a.kind == "int8" else "fp16",
                      "frac": achieved / peak if peak else None,
+                     # the peak scales with the shader clock; the clock inside
+                     # the kernel (measured per workgroup) is set by the chip's
+                     # power limit, below the 2.4 GHz the peak is quoted at
+                     "clock_ghz": dom.get("clock_ghz"),
+                     "frac_at_measured_clock": (achieved / (peak * dom["clock_ghz"] / NOMINAL_CLOCK_GHZ)
+                                                if peak and dom.get("clock_ghz") else None),
                      "traffic": (profiled_traffic(a.kind, a.slices) if a.workload == "tb_8192"
                                  else None),
                      "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE/WRITE_SIZE, "

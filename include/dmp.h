@@ -269,10 +269,12 @@ void dmp_tape_free(dmp_tape* tape);
 
 /* ---------------------------------------------------------------------
  * Kernel timing (instrumentation; process-wide state, not for concurrent
- * use from several host threads).  While enabled, the purification entry
- * points record a HIP event pair on the caller's stream around every
- * slice-GEMM launch (and launch without graph capture), and accumulate the
- * durations once each batch of iterations has completed.
+ * use from several host threads).  dmp_timing_enable(1) or (2): the
+ * purification entry points record a HIP event pair on the caller's stream
+ * around every slice-GEMM launch (and launch without graph capture), and
+ * accumulate the durations once each batch of iterations has completed;
+ * (2) also turns on the clock counters read by dmp_timing_clock (a few
+ * instructions and two atomic adds per workgroup); 0 turns timing off.
  *   which = 0: the squaring GEMM (P P), 1: the update GEMM (X2 P).
  *   *total_ms: summed kernel time; *launches: number of launches timed;
  *   *ops: summed algorithmic integer (or FP16) operations of those
@@ -282,6 +284,15 @@ void dmp_tape_free(dmp_tape* tape);
 void dmp_timing_enable(int on);
 void dmp_timing_reset(void);
 int dmp_timing_read(int which, double* total_ms, long long* launches, double* ops);
+
+/* Mean shader clock (GHz) inside the slice-GEMM launches of kind ``which``
+ * timed in mode 2 since the last dmp_timing_reset: every workgroup adds its
+ * span in shader-clock cycles (s_memtime) and in 100 MHz
+ * real-time ticks (s_memrealtime) to two device counters, and the clock is
+ * their ratio.  *ghz = 0 when nothing was timed.  Blocks for one small
+ * device-to-host copy.  The device counters are allocated on the first
+ * timed launch and kept until the process ends. */
+int dmp_timing_clock(int which, double* ghz);
 
 #ifdef __cplusplus
 }

@@ -26,7 +26,7 @@ EXPORTS = [
     "dmp_autotune_slices",
     "dmp_purify_fwd_tape", "dmp_purify_bwd_workspace_bytes", "dmp_purify_bwd",
     "dmp_tape_info", "dmp_tape_coefficients", "dmp_tape_free",
-    "dmp_timing_enable", "dmp_timing_reset", "dmp_timing_read",
+    "dmp_timing_enable", "dmp_timing_reset", "dmp_timing_read", "dmp_timing_clock",
 ]
 
 
@@ -92,6 +92,7 @@ _SIGS = {
     "dmp_timing_reset": (None, []),
     "dmp_timing_read": (_I, [_I, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong),
                              ctypes.POINTER(_D)]),
+    "dmp_timing_clock": (_I, [_I, ctypes.POINTER(_D)]),
 }
 
 

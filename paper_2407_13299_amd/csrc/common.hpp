@@ -188,6 +188,9 @@ struct GemmParams {
     // most to the least work (the hardware's round-robin over XCDs then
     // spreads every cost class evenly)
     int spread;
+    // nullable (kernel timing): [0] += shader-clock cycles and [1] += 100 MHz
+    // real-time ticks of every workgroup, from its start to its end
+    unsigned long long* clk;
 };
 
 }  // namespace dmp

@@ -90,6 +90,11 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
     const MatDesc d = p.descs ? p.descs[tile.mat] : p.one;
     const DevState* st = p.states ? p.states + d.state_index : nullptr;
     if (st != nullptr && st->done) return;
+    // clock stamps (timing mode): wave-uniform, so they live in scalar
+    // registers and leave the vector register budget of the loop untouched
+    const bool clocked = p.clk != nullptr;
+    const uint64_t clk_c = clocked ? __builtin_amdgcn_s_memtime() : 0;
+    const uint64_t clk_r = clocked ? __builtin_amdgcn_s_memrealtime() : 0;
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
@@ -375,6 +380,14 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
             }
             p.partials[int64_t(t) * kPartials + 0] = r0;
             p.partials[int64_t(t) * kPartials + 1] = r1;
+        }
+    }
+    if (clocked) {
+        const uint64_t dc = __builtin_amdgcn_s_memtime() - clk_c;
+        const uint64_t dr = __builtin_amdgcn_s_memrealtime() - clk_r;
+        if (threadIdx.x == 0) {
+            atomicAdd(p.clk + 0, static_cast<unsigned long long>(dc));
+            atomicAdd(p.clk + 1, static_cast<unsigned long long>(dr));
         }
     }
 }

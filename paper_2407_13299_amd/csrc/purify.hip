@@ -32,11 +32,17 @@ constexpr int kE0Blocks = 256;          // fixed grid of the P0 / energy pass
 // Kernel-timing instrumentation (see dmp_timing_*).
 struct TimingState {
     bool on = false;
+    bool clocks = false;   // also the per-workgroup clock counters
     double ms[2] = {0.0, 0.0};
     long long launches[2] = {0, 0};
     double ops[2] = {0.0, 0.0};
 };
 static TimingState g_timing;
+// Clock counters of the timed launches (device memory, allocated on the
+// first timed launch and kept until the process ends): per GEMM kind the
+// summed shader-clock cycles and real-time ticks of its workgroups.
+static unsigned long long* g_clk = nullptr;
+static int g_clk_device = -1;
 
 struct PendingTimer {
     hipEvent_t start, stop;
@@ -805,12 +811,24 @@ double gemm_ops(const GroupPlan& g, const int* n) {
 int timed_gemm(GroupPlan& g, const GemmParams& p, int which, double ops, hipStream_t s,
                std::vector<PendingTimer>* timers) {
     PendingTimer t{};
+    GemmParams q = p;
     if (timers) {
+        if (g_timing.clocks) {
+            int dev = 0;
+            DMP_CHECK_HIP(hipGetDevice(&dev));
+            if (g_clk == nullptr || g_clk_device != dev) {
+                // instrumentation only: one small buffer for the process
+                DMP_CHECK_HIP(hipMalloc(&g_clk, 4 * sizeof(unsigned long long)));
+                DMP_CHECK_HIP(hipMemset(g_clk, 0, 4 * sizeof(unsigned long long)));
+                g_clk_device = dev;
+            }
+            q.clk = g_clk + 2 * which;
+        }
         DMP_CHECK_HIP(hipEventCreate(&t.start));
         DMP_CHECK_HIP(hipEventCreate(&t.stop));
         DMP_CHECK_HIP(hipEventRecord(t.start, s));
     }
-    DMP_CHECK(launch_ozgemm(g.S, g.kind, p, g.ntiles, s));
+    DMP_CHECK(launch_ozgemm(g.S, g.kind, q, g.ntiles, s));
     if (timers) {
         DMP_CHECK_HIP(hipEventRecord(t.stop, s));
         t.which = which;
@@ -1178,12 +1196,43 @@ using namespace dmp;
 
 extern "C" {
 
-void dmp_timing_enable(int on) { g_timing.on = on != 0; }
+void dmp_timing_enable(int on) {
+    g_timing.on = on != 0;
+    g_timing.clocks = on == 2;
+}
 
 void dmp_timing_reset(void) {
-    const bool on = g_timing.on;
+    const bool on = g_timing.on, clocks = g_timing.clocks;
     g_timing = TimingState{};
     g_timing.on = on;
+    g_timing.clocks = clocks;
+    if (g_clk != nullptr) {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(g_clk_device);
+        (void)hipMemset(g_clk, 0, 4 * sizeof(unsigned long long));
+        (void)hipSetDevice(cur);
+    }
+}
+
+int dmp_timing_clock(int which, double* ghz) {
+    clear_error();
+    if (which < 0 || which > 1 || ghz == nullptr) {
+        set_error("which must be 0 or 1 and ghz non-null");
+        return DMP_EINVAL;
+    }
+    *ghz = 0.0;
+    if (g_clk == nullptr) return DMP_OK;
+    unsigned long long c[2] = {0, 0};
+    int cur = 0;
+    DMP_CHECK_HIP(hipGetDevice(&cur));
+    DMP_CHECK_HIP(hipSetDevice(g_clk_device));
+    const hipError_t e = hipMemcpy(c, g_clk + 2 * which, sizeof(c), hipMemcpyDeviceToHost);
+    DMP_CHECK_HIP(hipSetDevice(cur));
+    DMP_CHECK_HIP(e);
+    // the real-time counter runs at 100 MHz
+    if (c[1] > 0) *ghz = double(c[0]) / (double(c[1]) * 10.0);
+    return DMP_OK;
 }
 
 int dmp_timing_read(int which, double* total_ms, long long* launches, double* ops) {

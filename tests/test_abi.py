@@ -120,6 +120,14 @@ def test_argument_errors_without_device_work(lib):
     assert st == -4
 
 
+def test_timing_clock_without_timed_launches(lib):
+    ghz = ctypes.c_double(-1.0)
+    assert lib.dmp_timing_clock(2, ctypes.byref(ghz)) == -1
+    assert lib.dmp_timing_clock(0, None) == -1
+    # nothing timed in this process yet: 0 GHz, no device call made
+    assert lib.dmp_timing_clock(1, ctypes.byref(ghz)) == 0 and ghz.value == 0.0
+
+
 def test_autotune_table_monotone(lib):
     prev = 0
     for n in (64, 256, 1024, 4096, 8192):

@@ -68,3 +68,35 @@ def test_gemm_on_a_side_stream(batched):
     torch.cuda.synchronize()
     del junk
     assert np.array_equal(c.cpu().numpy(), ref)
+
+
+def test_timing_clock_is_measured_inside_the_gemm():
+    """With kernel timing on, the GEMM workgroups report their shader clock:
+    a plausible value (the MI355X runs at up to 2.4 GHz), and a reset clears it."""
+    from paper_2407_13299_amd import _lib
+    from paper_2407_13299_amd.workloads import spectrum_hamiltonian
+    import ctypes
+    lib = _lib.load()
+    h, _, _ = spectrum_hamiltonian(700, 350, seed=2)
+    hd = dev(h)
+    lib.dmp_timing_enable(1)
+    try:
+        lib.dmp_timing_reset()
+        dmp.purify(hd, 350, tol=1e-10, slices=7)
+        torch.cuda.synchronize()
+        ghz = ctypes.c_double(-1.0)
+        assert lib.dmp_timing_clock(0, ctypes.byref(ghz)) == 0 and ghz.value == 0.0   # mode 1: events only
+        lib.dmp_timing_enable(2)
+        lib.dmp_timing_reset()
+        dmp.purify(hd, 350, tol=1e-10, slices=7)
+        torch.cuda.synchronize()
+        for which in (0, 1):
+            ghz = ctypes.c_double()
+            assert lib.dmp_timing_clock(which, ctypes.byref(ghz)) == 0
+            assert 0.3 < ghz.value < 3.0, ghz.value
+        lib.dmp_timing_reset()
+        ghz = ctypes.c_double(-1.0)
+        assert lib.dmp_timing_clock(0, ctypes.byref(ghz)) == 0 and ghz.value == 0.0
+    finally:
+        lib.dmp_timing_enable(0)
+        lib.dmp_timing_reset()
