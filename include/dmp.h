@@ -250,7 +250,8 @@ int dmp_autotune_slices(int n, double target, dmp_kind kind);
  * dependence of every c_k on P_k and of the initial guess on tr H and the
  * Gershgorin bounds.  Iterates between checkpoints are recomputed with the
  * same products, so every ckpt_stride gives the same Hbar bit for bit.
- * Each backward step costs 3 products plus the recomputation of 2.
+ * Each backward step costs 3 products (M = Y P and M P in full, the
+ * symmetric P M on its upper triangle) plus the recomputation of 2.
  * ------------------------------------------------------------------- */
 typedef struct dmp_tape dmp_tape;
 int dmp_purify_fwd_tape(const double* H, int n, int nocc, double tol,

@@ -13,7 +13,7 @@
 // P_{k+1} = a P + b P^2 + g P^3 on the recorded branch:
 //   M = Y P,  MP = M P (= Y P^2),  PM = P M (= P Y P)        (3 Ozaki GEMMs)
 //   cbar = a' <Y, P> + b' <Y, P^2> + g' <Y, P^3>,  <Y, P^3> = sum MP o P
-//   Y <- a Y + b (M + M^T) + g (MP + MP^T + (PM + PM^T) / 2)
+//   Y <- a Y + b (M + M^T) + g (MP + MP^T + PM)
 //        + cbar ((2P - 3X2) t1 - t2 (I - 2P)) / t1^2     (no cbar if clamped)
 // and finally, for P0 = lam (mu I - H) + theta I with mu = tr H / n and lam
 // from the Gershgorin bounds (the extremal row held fixed):
@@ -45,6 +45,7 @@ struct OzCtx {
     int* eb = nullptr;
     uint64_t* ma = nullptr;
     uint64_t* mb = nullptr;
+    uint64_t* mc = nullptr;     // column maxima of M = Y P (its column split)
     double* partials = nullptr;
     double* rows = nullptr;
     int* rowbad = nullptr;
@@ -71,6 +72,7 @@ void carve_ctx(Carver& c, OzCtx& x, int n, int S, dmp_kind kind) {
     x.eb = c.take<int>(round_up(n, kPad));
     x.ma = c.take<uint64_t>(round_up(n, kPad));
     x.mb = c.take<uint64_t>(round_up(n, kPad));
+    x.mc = c.take<uint64_t>(round_up(n, kPad));
     x.partials = c.take<double>(size_t(std::max(upper_tile_count(n), 1)) * kPartials);
     x.rows = c.take<double>(3 * size_t(n));
     x.rowbad = c.take<int>(n);
@@ -165,15 +167,20 @@ int forward_iteration(const OzCtx& x, const double* P_in, double* X2_out, double
 }
 
 // C = A B for n x n operands already split: (pa, ea) rows of A, (pb, eb)
-// columns of B.
+// columns of B.  rowmax / colmax (nullable, zeroed beforehand) receive the
+// maxima of |C| per row / column for the splits of C.  ``sym``: C is known
+// to be symmetric; only its upper tiles are computed and mirrored.
 int gemm_store(const OzCtx& x, const uint8_t* pa, const int* ea, const uint8_t* pb,
-               const int* eb, double* out, hipStream_t s) {
+               const int* eb, double* out, uint64_t* rowmax, uint64_t* colmax, bool sym,
+               hipStream_t s) {
     GemmParams p{};
-    p.tiles = x.tiles_full;
+    p.tiles = sym ? x.tiles_up : x.tiles_full;
     p.one = gemm_desc(x, pa, ea, pb, eb, out);
     p.one.state_index = -1;
-    p.mode = EPI_STORE;
-    return launch_ozgemm(x.S, x.kind, p, x.nt_full, s);
+    p.one.rowmax = rowmax;
+    p.one.colmax = colmax;
+    p.mode = sym ? EPI_STORE_SYM : EPI_STORE;
+    return launch_ozgemm(x.S, x.kind, p, sym ? x.nt_up : x.nt_full, s);
 }
 
 __device__ inline double wsum(double v) {
@@ -260,26 +267,26 @@ __global__ __launch_bounds__(256) void k_adj_cbar(const double* dots, double c, 
     }
 }
 
-// Y' = a Y + b (M + M^T) + g (MP + MP^T + (PM + PM^T)/2) + cbar dc, on tile
-// pairs (I <= J); symmetric, written to both tiles.
+// Y' = a Y + b (M + M^T) + g (MP + MP^T + PM) + cbar dc, on tile pairs
+// (I <= J); symmetric, written to both tiles.  PM = P Y P is stored exactly
+// symmetric (upper tiles mirrored), so it needs no transpose.
 __global__ __launch_bounds__(256) void k_adj_combine(const double* Y, const double* M,
                                                      const double* MP, const double* PM,
                                                      const double* P, const double* X2,
                                                      double* Yn, int n, double a, double b,
                                                      double g, double t1, double t2,
                                                      const double* scal, const int2* pairs) {
-    __shared__ double tM[32][33], tMP[32][33], tPM[32][33], tO[32][33];
+    __shared__ double tM[32][33], tMP[32][33], tO[32][33];
     const int2 pr = pairs[blockIdx.x];
     const int I = pr.x, J = pr.y, tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     const double cbar = scal[0];
     const double inv = (cbar != 0.0) ? 1.0 / (t1 * t1) : 0.0;
-    for (int r = ty; r < 32; r += 8) {      // tile (J, I) of M, MP, PM
+    for (int r = ty; r < 32; r += 8) {      // tile (J, I) of M and MP
         const int i = J * 32 + r, j = I * 32 + tx;
         const bool ok = i < n && j < n;
         const int64_t o = int64_t(i) * n + j;
         tM[r][tx] = ok ? M[o] : 0.0;
         tMP[r][tx] = ok ? MP[o] : 0.0;
-        tPM[r][tx] = ok ? PM[o] : 0.0;
     }
     __syncthreads();
     for (int r = ty; r < 32; r += 8) {
@@ -288,7 +295,7 @@ __global__ __launch_bounds__(256) void k_adj_combine(const double* Y, const doub
         if (i < n && j < n) {
             const int64_t o = int64_t(i) * n + j;
             const double p = P[o], x2 = X2[o];
-            v = a * Y[o] + b * (M[o] + tM[tx][r]) + g * (MP[o] + tMP[tx][r] + 0.5 * (PM[o] + tPM[tx][r]));
+            v = a * Y[o] + b * (M[o] + tM[tx][r]) + g * (MP[o] + tMP[tx][r] + PM[o]);
             if (cbar != 0.0) v += cbar * ((2.0 * p - 3.0 * x2) * t1 - t2 * ((i == j ? 1.0 : 0.0) - 2.0 * p)) * inv;
             Yn[o] = v;
         }
@@ -647,14 +654,24 @@ int dmp_purify_bwd(const dmp_tape* t, const double* Pbar, double* Hbar, void* ws
         for (int j = end - 1; j >= start; --j) {
             const double* P = segP[j - start];
             const double* X2 = segX[j - start];
-            // M = Y P, MP = M P, PM = P M
-            DMP_CHECK(launch_split(split_of(x, Y, false, x.ma, x.ea, x.pa, -1), x.S, x.kind, nullptr, s));
-            DMP_CHECK(launch_split(split_of(x, P, false, x.mb, x.eb, x.pb, -1), x.S, x.kind, nullptr, s));
-            DMP_CHECK(gemm_store(x, x.pa, x.ea, x.pb, x.eb, M, s));
-            DMP_CHECK(launch_split(split_of(x, M, false, x.ma, x.ea, x.pa, -1), x.S, x.kind, nullptr, s));
-            DMP_CHECK(gemm_store(x, x.pa, x.ea, x.pb, x.eb, MP, s));
-            DMP_CHECK(launch_split(split_of(x, M, true, x.ma, x.ea, x.pa, -1), x.S, x.kind, nullptr, s));
-            DMP_CHECK(gemm_store(x, x.pb, x.eb, x.pa, x.ea, PM, s));
+            // M = Y P, MP = M P, PM = P M.  The row and column maxima of M
+            // come from its product's epilogue (x.ma, x.mc: zeroed by the
+            // digit kernels of the two splits before it, once their own
+            // maxima are no longer read), so M's two splits run only their
+            // digit kernels.  PM = P Y P is symmetric: upper tiles, mirrored.
+            SplitDesc sy = split_of(x, Y, false, x.ma, x.ea, x.pa, -1);
+            sy.clear = x.mc;
+            DMP_CHECK(launch_split(sy, x.S, x.kind, nullptr, s));
+            SplitDesc sp = split_of(x, P, false, x.mb, x.eb, x.pb, -1);
+            sp.clear = x.ma;
+            DMP_CHECK(launch_split(sp, x.S, x.kind, nullptr, s));
+            DMP_CHECK(gemm_store(x, x.pa, x.ea, x.pb, x.eb, M, x.ma, x.mc, false, s));
+            DMP_CHECK(launch_split_digits(split_of(x, M, false, x.ma, x.ea, x.pa, -1), x.S, x.kind,
+                                          nullptr, s));
+            DMP_CHECK(gemm_store(x, x.pa, x.ea, x.pb, x.eb, MP, nullptr, nullptr, false, s));
+            DMP_CHECK(launch_split_digits(split_of(x, M, true, x.mc, x.ea, x.pa, -1), x.S, x.kind,
+                                          nullptr, s));
+            DMP_CHECK(gemm_store(x, x.pb, x.eb, x.pa, x.ea, PM, nullptr, nullptr, true, s));
             const double cc = t->c[j];
             const int br = t->branch[j];
             double a, bb, g;

@@ -94,9 +94,11 @@ struct MatDesc {
     const double* X2;      // square of the iterate
     const double* H;       // Hamiltonian
     double* out;           // output matrix
-    double* out2;          // second output (mirror target / spare)
-    uint64_t* rowmax;      // nullable (purification modes): atomicMax of the
-                           // bit pattern of |out_ij| into rowmax[i], for the
+    uint64_t* colmax;      // nullable (EPI_STORE): atomicMax of the bit pattern
+                           // of |out_ij| into colmax[j]; zeroed beforehand
+    uint64_t* rowmax;      // nullable: atomicMax of the bit pattern of
+                           // |out_ij| into rowmax[i] (and, in the mirrored
+                           // modes, of |out_ji| into rowmax[j]), for the
                            // next split; zeroed beforehand by the caller
     int64_t a_rb_stride;   // bytes between 32-row blocks of pa
     int64_t b_rb_stride;   // bytes between 32-row blocks of pb
@@ -171,6 +173,8 @@ enum EpiMode : int {
     EPI_UPDATE = 2,    // P' = a P + b X2 + g X2 P (upper, mirrored) + E, tr;
                        // g == 0 skips the products
     EPI_SQUARE_TRS4 = 3,  // X2 = X X (upper, mirrored) + tr F, tr G of TRS4
+    EPI_STORE_SYM = 4, // C = A B known to be symmetric (square): upper tiles,
+                       // C_ij stored and mirrored, no traces
 };
 
 constexpr int kPartials = 2;   // partial sums written per tile

@@ -50,6 +50,8 @@ int native_dgemm(hipStream_t stream, bool ta, bool tb, int m, int n, int k, cons
                  int lda, const double* B, int ldb, double* C, int ldc);
 
 int launch_split(const SplitDesc& d, int S, dmp_kind kind, const DevState* st, hipStream_t s);
+int launch_split_digits(const SplitDesc& d, int S, dmp_kind kind, const DevState* st,
+                        hipStream_t stream);
 int launch_split_grouped_rowmax(const SplitDesc* descs_dev, int count, int units,
                                 const DevState* st, hipStream_t stream);
 int launch_split_grouped_digits(const SplitDesc* descs_dev, int count, int units, int S,

@@ -22,7 +22,10 @@
 //   h = G_{S+1};  h = h 2^-8 + G_g  (g = S .. 2);  C = h 2^(e_i + f_j - 12),
 // equal to adding the scaled group sums smallest first (power-of-two
 // scalings are exact).  Then, by mode:
-//   EPI_STORE   C (rows < M, columns < N)
+//   EPI_STORE   C (rows < M, columns < N); optionally the row and column
+//               maxima of |C| (bit patterns, atomicMax) for the next splits
+//   EPI_STORE_SYM  C = A B known to be symmetric (square): upper tiles only,
+//               C_ij stored and mirrored (optionally its row maxima)
 //   EPI_SQUARE  X2 = P P for row <= col, mirrored; tile partials of
 //               tr(P - X2) and sum_ij X2_ij (delta_ij - P_ij) = tr(X2 - P^3)
 //   EPI_UPDATE  P' = alpha P + beta X2 + gamma (X2 P) for row <= col,
@@ -71,7 +74,10 @@ __device__ inline double wave_sum(double v) {
 // TERMS > 0: the Markidis product (Sec. 4.5) on the same tiles: S = 2 FP16
 // planes (high, low parts), the first TERMS of A0 B0, A0 B1, A1 B0, A1 B1
 // accumulated in one FP32 accumulator, and C = acc 2^(e_i + f_j).
-template <int S, bool FP16, int TERMS = 0>
+// PUR: the purification epilogues (EPI_SQUARE, EPI_UPDATE, EPI_SQUARE_TRS4);
+// otherwise the plain ones (EPI_STORE, EPI_STORE_SYM).  Two instantiations
+// keep each epilogue free of the other family's code.
+template <int S, bool FP16, int TERMS = 0, bool PUR = false>
 __global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
     constexpr int BLOCKS = 6 * S;                 // 1 KiB blocks per chunk
     constexpr int STAGE = BLOCKS * kFragBytes;
@@ -228,7 +234,7 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
     };
     // an update whose product weight is zero (a TRS4 step without the
     // second product) keeps only the elementwise part
-    const bool no_product = p.mode == EPI_UPDATE && st != nullptr && st->gamma == 0.0;
+    const bool no_product = PUR && p.mode == EPI_UPDATE && st != nullptr && st->gamma == 0.0;
     if (!no_product) {
         for (int kc = -2; kc < KC; kc += 2) {
             step(kc, 0, r0, r1);
@@ -242,7 +248,7 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
     const int fj = d.eb[col];
     const int mode = p.mode;
     double alpha = 0.0, beta = 0.0, gamma = 0.0;
-    if (mode == EPI_UPDATE) {
+    if (PUR && mode == EPI_UPDATE) {
         alpha = st->alpha;
         beta = st->beta;
         gamma = st->gamma;
@@ -254,7 +260,10 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
     // NaN above an infinity); per element reduced over the 32 lanes of a
     // half-wavefront (the lanes of one row), and per column over the lane's
     // elements (the mirror's rows)
-    const bool rowmax = mode != EPI_STORE && d.rowmax != nullptr;
+    // trace partials and the P, X2, H inputs: the purification modes only
+    constexpr bool traces = PUR;
+    const bool rowmax = d.rowmax != nullptr;
+    uint64_t* const colmax_dst = (!PUR && mode == EPI_STORE) ? d.colmax : d.rowmax;
     uint64_t mine = 0;
     uint64_t cmax = 0;
     auto absbits = [](double x) __attribute__((always_inline)) {
@@ -283,19 +292,25 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
     // uses below, past the loads, and the accumulators stay live beside them.
 #pragma unroll
     for (int v = 0; v < 16; ++v) asm volatile("" : "+v"(hsum[v]));
+    // The base pointers pass through the same kind of empty statement, so the
+    // loads below depend on this point and are not hoisted above the main
+    // loop (where their results would hold registers all along).
+    const int* ea = d.ea;
+    const double *Pin = d.P, *X2in = d.X2, *Hin = d.H;
+    asm volatile("" : "+s"(ea), "+s"(Pin), "+s"(X2in), "+s"(Hin));
     int eiv[16];
     double pv[16], xv[16], hv[16];
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         const int row = row0 + (v >> 2) * 8 + (v & 3);
-        eiv[v] = d.ea[row];
+        eiv[v] = ea[row];
         pv[v] = xv[v] = hv[v] = 0.0;
-        if (mode != EPI_STORE && row < n && col < n && row <= col) {
+        if (traces && row < n && col < n && row <= col) {
             const int64_t ij = int64_t(row) * n + col;
-            pv[v] = d.P[ij];
+            pv[v] = Pin[ij];
             if (mode == EPI_UPDATE) {
-                xv[v] = d.X2[ij];
-                hv[v] = d.H[ij];
+                xv[v] = X2in[ij];
+                hv[v] = Hin[ij];
             }
         }
     }
@@ -309,12 +324,21 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
                          : (ei >= kNonFiniteExp || fj >= kNonFiniteExp)
                              ? __builtin_nan("")
                              : ldexp(h, ei + fj - shift);
-        if (mode == EPI_STORE) {
-            if (row < d.M && col < d.N) d.out[int64_t(row) * d.ldc + col] = c;
-            continue;
-        }
         uint64_t bits = 0;
-        if (row < n && col < n && row <= col) {
+        if (!PUR && mode == EPI_STORE) {
+            if (row < d.M && col < d.N) {
+                d.out[int64_t(row) * d.ldc + col] = c;
+                bits = absbits(c);
+                cmax = bits > cmax ? bits : cmax;
+            }
+        } else if (!PUR) {   // EPI_STORE_SYM
+            if (row < n && col < n && row <= col) {
+                d.out[int64_t(row) * n + col] = c;
+                if (row != col) d.out[int64_t(col) * n + row] = c;
+                bits = absbits(c);
+                cmax = bits > cmax ? bits : cmax;
+            }
+        } else if (row < n && col < n && row <= col) {
             const bool diag = (row == col);
             const double mult = diag ? 1.0 : 2.0;
             const int64_t ij = int64_t(row) * n + col, ji = int64_t(col) * n + row;
@@ -353,17 +377,20 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
     if (rowmax) {
         const int myv = lane & 31;
         const int myrow = row0 + (myv >> 2) * 8 + (myv & 3);
-        if (myv < 16 && myrow < n && mine != 0)
+        if (myv < 16 && myrow < d.M && mine != 0)
             atomicMax(reinterpret_cast<unsigned long long*>(d.rowmax) + myrow,
                       static_cast<unsigned long long>(mine));
-        // columns: both halves hold rows of the same column
+    }
+    if (colmax_dst != nullptr) {
+        // columns: both halves hold rows of the same column; in the mirrored
+        // modes the column's elements are the mirror's row ``col``
         const uint64_t o = static_cast<uint64_t>(__shfl_xor(static_cast<long long>(cmax), 32, 64));
         cmax = o > cmax ? o : cmax;
-        if (lane < 32 && col < n && cmax != 0)
-            atomicMax(reinterpret_cast<unsigned long long*>(d.rowmax) + col,
+        if (lane < 32 && col < d.N && cmax != 0)
+            atomicMax(reinterpret_cast<unsigned long long*>(colmax_dst) + col,
                       static_cast<unsigned long long>(cmax));
     }
-    if (mode != EPI_STORE) {
+    if (traces) {
         s0 = wave_sum(s0);
         s1 = wave_sum(s1);
         if (lane == 0) {
@@ -392,12 +419,21 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
     }
 }
 
+static bool purification_mode(int mode) {
+    return mode == EPI_SQUARE || mode == EPI_UPDATE || mode == EPI_SQUARE_TRS4;
+}
+
 template <int S>
 static void launch_s(bool fp16, const GemmParams& p, int ntiles, hipStream_t stream) {
-    if (fp16)
-        k_ozgemm<S, true><<<ntiles, kGemmThreads, 0, stream>>>(p);
+    const bool pur = purification_mode(p.mode);
+    if (fp16 && pur)
+        k_ozgemm<S, true, 0, true><<<ntiles, kGemmThreads, 0, stream>>>(p);
+    else if (fp16)
+        k_ozgemm<S, true, 0, false><<<ntiles, kGemmThreads, 0, stream>>>(p);
+    else if (pur)
+        k_ozgemm<S, false, 0, true><<<ntiles, kGemmThreads, 0, stream>>>(p);
     else
-        k_ozgemm<S, false><<<ntiles, kGemmThreads, 0, stream>>>(p);
+        k_ozgemm<S, false, 0, false><<<ntiles, kGemmThreads, 0, stream>>>(p);
 }
 
 using GemmFn = void (*)(bool, const GemmParams&, int, hipStream_t);
@@ -407,7 +443,10 @@ static const GemmFn kGemm[kMaxSlices + 1] = {
 
 template <int T>
 static void launch_terms(const GemmParams& p, int ntiles, hipStream_t stream) {
-    k_ozgemm<2, true, T><<<ntiles, kGemmThreads, 0, stream>>>(p);
+    if (purification_mode(p.mode))
+        k_ozgemm<2, true, T, true><<<ntiles, kGemmThreads, 0, stream>>>(p);
+    else
+        k_ozgemm<2, true, T, false><<<ntiles, kGemmThreads, 0, stream>>>(p);
 }
 
 using TermsFn = void (*)(const GemmParams&, int, hipStream_t);

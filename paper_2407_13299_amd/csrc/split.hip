@@ -370,6 +370,19 @@ int launch_split(const SplitDesc& d, int S, dmp_kind kind, const DevState* st,
     return DMP_OK;
 }
 
+// The digit kernel alone, for an operand whose maxima (d.maxbits: row maxima,
+// or column maxima when d.trans) an earlier product's epilogue accumulated.
+int launch_split_digits(const SplitDesc& d, int S, dmp_kind kind, const DevState* st,
+                        hipStream_t stream) {
+    if (round_up(d.R, kPad) == 0) return DMP_OK;
+    if (kind == DMP_MARKIDIS_FP16)
+        k_digits<2, true, true><<<split_units_digits(d.R, d.KC), 256, 0, stream>>>(nullptr, 0, d, st);
+    else
+        kDigits[S](kind == DMP_OZ_FP16, nullptr, 0, d, st, split_units_digits(d.R, d.KC), stream);
+    DMP_CHECK_HIP(hipGetLastError());
+    return DMP_OK;
+}
+
 // Grouped split of count operands (row splits only); descs in device memory
 // with ub_rowmax / ub_digits the first unit of every matrix in each kernel.
 int launch_split_grouped_rowmax(const SplitDesc* descs_dev, int count, int units,
