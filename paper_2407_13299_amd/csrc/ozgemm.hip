@@ -255,12 +255,13 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
     }
     const int n = d.M;
     double s0 = 0.0, s1 = 0.0;
-    // row maxima of the output for the next split (purification modes):
-    // bit patterns of |value| (their integer order is the numeric order, a
-    // NaN above an infinity); per element reduced over the 32 lanes of a
-    // half-wavefront (the lanes of one row), and per column over the lane's
-    // elements (the mirror's rows)
-    // trace partials and the P, X2, H inputs: the purification modes only
+    // Maxima of |output| for the next splits, as bit patterns (for
+    // non-negative doubles the integer order is the numeric order, a NaN
+    // above an infinity): per row, each element reduced over the 32 lanes of
+    // a half-wavefront (the lanes of one row); per column, over the lane's 16
+    // elements.  In the mirrored modes a column of the tile is a row of the
+    // mirror, so both go to rowmax; in EPI_STORE the columns go to colmax.
+    // Trace partials and the P, X2, H inputs: the purification modes only.
     constexpr bool traces = PUR;
     const bool rowmax = d.rowmax != nullptr;
     uint64_t* const colmax_dst = (!PUR && mode == EPI_STORE) ? d.colmax : d.rowmax;
