@@ -54,10 +54,13 @@ struct OzCtx {
     double* scal = nullptr;     // [8] device scalars
     PurDesc* pd = nullptr;
     DevState* st = nullptr;
-    const Tile* tiles_up = nullptr;
+    const Tile* tiles_up = nullptr;     // 128-row upper tiles (symmetric store)
     int nt_up = 0;
     const Tile* tiles_full = nullptr;
     int nt_full = 0;
+    int rb = 4;                         // purification products: the same tiles
+    const Tile* tiles_pur = nullptr;    // as dmp_purify uses for this n and S
+    int nt_pur = 0;
 };
 
 void carve_ctx(Carver& c, OzCtx& x, int n, int S, dmp_kind kind) {
@@ -65,6 +68,7 @@ void carve_ctx(Carver& c, OzCtx& x, int n, int S, dmp_kind kind) {
     x.S = S;
     x.kind = kind;
     x.KC = int(chunks_of(n, kind));
+    x.rb = tile_blocks_for(kind, S, n);
     x.rb_stride = int64_t(x.KC) * S * kFragBytes;
     x.pa = c.take<uint8_t>(plane_bytes(n, n, S, kind));
     x.pb = c.take<uint8_t>(plane_bytes(n, n, S, kind));
@@ -73,7 +77,7 @@ void carve_ctx(Carver& c, OzCtx& x, int n, int S, dmp_kind kind) {
     x.ma = c.take<uint64_t>(round_up(n, kPad));
     x.mb = c.take<uint64_t>(round_up(n, kPad));
     x.mc = c.take<uint64_t>(round_up(n, kPad));
-    x.partials = c.take<double>(size_t(std::max(upper_tile_count(n), 1)) * kPartials);
+    x.partials = c.take<double>(size_t(std::max(upper_tile_count(n, 32 * x.rb), 1)) * kPartials);
     x.rows = c.take<double>(3 * size_t(n));
     x.rowbad = c.take<int>(n);
     x.e0 = c.take<double>(e0_blocks());
@@ -90,6 +94,8 @@ int bind_ctx(OzCtx& x, const double* H, int nocc, double* P0, hipStream_t s) {
     DMP_CHECK(cached_tiles(tm, tn, false, &x.tiles_full));
     x.nt_up = upper_tile_count(x.n);
     x.nt_full = tm * tn;
+    DMP_CHECK(cached_tiles(tile_rows(x.n, 32 * x.rb), tn, true, &x.tiles_pur, 32 * x.rb));
+    x.nt_pur = upper_tile_count(x.n, 32 * x.rb);
     PurDesc d{};
     d.H = H;
     d.Pb[0] = P0;
@@ -101,7 +107,7 @@ int bind_ctx(OzCtx& x, const double* H, int nocc, double* P0, hipStream_t s) {
     d.n = x.n;
     d.nocc = nocc;
     d.part_begin = 0;
-    d.part_end = x.nt_up;
+    d.part_end = x.nt_pur;
     DMP_CHECK_HIP(hipMemcpyAsync(x.pd, &d, sizeof(d), hipMemcpyHostToDevice, s));
     DMP_CHECK_HIP(hipStreamSynchronize(s));
     return DMP_OK;
@@ -147,13 +153,13 @@ int forward_iteration(const OzCtx& x, const double* P_in, double* X2_out, double
                       bool finalize, hipStream_t s) {
     DMP_CHECK(launch_split(split_of(x, P_in, false, x.ma, x.ea, x.pa, 0), x.S, x.kind, x.st, s));
     GemmParams p{};
-    p.tiles = x.tiles_up;
+    p.tiles = x.tiles_pur;
     p.one = gemm_desc(x, x.pa, x.ea, x.pa, x.ea, X2_out);
     p.one.P = P_in;
     p.partials = x.partials;
     p.states = x.st;
     p.mode = EPI_SQUARE;
-    DMP_CHECK(launch_ozgemm(x.S, x.kind, p, x.nt_up, s));
+    DMP_CHECK(launch_ozgemm(x.S, x.kind, p, x.nt_pur, s, x.rb));
     DMP_CHECK(launch_finalize_coef(x.pd, x.st, 1, s));
     DMP_CHECK(launch_split(split_of(x, X2_out, false, x.mb, x.eb, x.pb, 0), x.S, x.kind, x.st, s));
     p.one = gemm_desc(x, x.pb, x.eb, x.pa, x.ea, P_out);
@@ -161,7 +167,7 @@ int forward_iteration(const OzCtx& x, const double* P_in, double* X2_out, double
     p.one.X2 = X2_out;
     p.one.H = x.H;
     p.mode = EPI_UPDATE;
-    DMP_CHECK(launch_ozgemm(x.S, x.kind, p, x.nt_up, s));
+    DMP_CHECK(launch_ozgemm(x.S, x.kind, p, x.nt_pur, s, x.rb));
     if (finalize) DMP_CHECK(launch_finalize_iter(x.pd, x.st, 1, s));
     return DMP_OK;
 }

@@ -20,46 +20,46 @@ void set_error(const char* fmt, ...) {
 
 void clear_error() { g_error[0] = '\0'; }
 
-bool tile_in_upper(int i, int j) { return kTileN * j + kTileN - 1 >= kTileM * i; }
+static bool tile_in_upper(int i, int j, int TM) { return kTileN * j + kTileN - 1 >= TM * i; }
 
-void append_tiles(std::vector<Tile>& out, int tm, int tn, bool upper, uint32_t mat) {
+void append_tiles(std::vector<Tile>& out, int tm, int tn, bool upper, uint32_t mat, int TM) {
     // super-tiles of GI x GJ tiles = 512 x 512 elements
-    constexpr int GI = 512 / kTileM, GJ = 512 / kTileN;
+    const int GI = 512 / TM, GJ = 512 / kTileN;
     const int sm = (tm + GI - 1) / GI, sn = (tn + GJ - 1) / GJ;
     for (int si = 0; si < sm; ++si)
         for (int sj = 0; sj < sn; ++sj)
             for (int i = si * GI; i < std::min(tm, si * GI + GI); ++i)
                 for (int j = sj * GJ; j < std::min(tn, sj * GJ + GJ); ++j) {
-                    if (upper && !tile_in_upper(i, j)) continue;
+                    if (upper && !tile_in_upper(i, j, TM)) continue;
                     out.push_back(Tile{uint16_t(i), uint16_t(j), mat});
                 }
 }
 
-int tile_rows(int m) { return int(round_up(m, kTileM) / kTileM); }
+int tile_rows(int m, int TM) { return int(round_up(m, TM) / TM); }
 int tile_cols(int n) { return int(round_up(n, kTileN) / kTileN); }
 
-int upper_tile_count(int n) {
-    const int tm = tile_rows(n), tn = tile_cols(n);
+int upper_tile_count(int n, int TM) {
+    const int tm = tile_rows(n, TM), tn = tile_cols(n);
     int c = 0;
     for (int i = 0; i < tm; ++i)
-        for (int j = 0; j < tn; ++j) c += tile_in_upper(i, j) ? 1 : 0;
+        for (int j = 0; j < tn; ++j) c += tile_in_upper(i, j, TM) ? 1 : 0;
     return c;
 }
 
-int cached_tiles(int tm, int tn, bool upper, const Tile** out) {
+int cached_tiles(int tm, int tn, bool upper, const Tile** out, int TM) {
     static std::mutex mu;
-    static std::map<std::tuple<int, int, int, bool>, Tile*> cache;
+    static std::map<std::tuple<int, int, int, bool, int>, Tile*> cache;
     int dev = 0;
     DMP_CHECK_HIP(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lock(mu);
-    auto key = std::make_tuple(dev, tm, tn, upper);
+    auto key = std::make_tuple(dev, tm, tn, upper, TM);
     auto it = cache.find(key);
     if (it != cache.end()) {
         *out = it->second;
         return DMP_OK;
     }
     std::vector<Tile> host;
-    append_tiles(host, tm, tn, upper, 0);
+    append_tiles(host, tm, tn, upper, 0, TM);
     Tile* devp = nullptr;
     DMP_CHECK_HIP(hipMalloc(&devp, std::max<size_t>(1, host.size()) * sizeof(Tile)));
     if (!host.empty())

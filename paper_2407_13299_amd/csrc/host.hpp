@@ -30,17 +30,19 @@ private:
     size_t off_ = 0;
 };
 
-// Order of the 128 x 64 output tiles of one matrix: 512 x 512 super-tiles,
-// row-major over super-tiles and within each; ``upper`` keeps the tiles that
-// reach the upper triangle (column >= row somewhere in the tile).
-void append_tiles(std::vector<Tile>& out, int tm, int tn, bool upper, uint32_t mat);
-int tile_rows(int m);
+// Order of the TM x 64 output tiles of one matrix (TM = 128, or 64 for the
+// 64-row variant): 512 x 512 super-tiles, row-major over super-tiles and
+// within each; ``upper`` keeps the tiles that reach the upper triangle
+// (column >= row somewhere in the tile).
+void append_tiles(std::vector<Tile>& out, int tm, int tn, bool upper, uint32_t mat,
+                  int TM = kTileM);
+int tile_rows(int m, int TM = kTileM);
 int tile_cols(int n);
-int upper_tile_count(int n);
+int upper_tile_count(int n, int TM = kTileM);
 
 // Device copy of the tile order of a single tm x tn product, cached per
 // device for the life of the process.
-int cached_tiles(int tm, int tn, bool upper, const Tile** out);
+int cached_tiles(int tm, int tn, bool upper, const Tile** out, int TM = kTileM);
 
 // rocBLAS handle of the current device (created once), bound to ``stream``.
 int blas_handle(hipStream_t stream, rocblas_handle* out);
@@ -60,7 +62,14 @@ int split_units_rowmax(int R);
 int split_units_digits(int R, int KC);
 
 struct GemmParams;
-int launch_ozgemm(int S, dmp_kind kind, const GemmParams& p, int ntiles, hipStream_t stream);
+// 32-row blocks per slice-GEMM tile of an n x n Ozaki purification product
+// (2: 64-row tiles for small n, else 4); a function of (kind, S, n) only
+int tile_blocks_for(dmp_kind kind, int S, int n);
+
+// rb: 32-row blocks per tile of the left operand (4, or 2 for the 64-row
+// variant of the Ozaki purification products)
+int launch_ozgemm(int S, dmp_kind kind, const GemmParams& p, int ntiles, hipStream_t stream,
+                  int rb = 4);
 
 int native_dsyrk_upper(hipStream_t stream, int n, const double* A, double* C);
 int native_dsyrkx_upper(hipStream_t stream, int n, const double* A, const double* B, double* C);

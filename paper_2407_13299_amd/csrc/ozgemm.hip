@@ -77,11 +77,16 @@ __device__ inline double wave_sum(double v) {
 // PUR: the purification epilogues (EPI_SQUARE, EPI_UPDATE, EPI_SQUARE_TRS4);
 // otherwise the plain ones (EPI_STORE, EPI_STORE_SYM).  Two instantiations
 // keep each epilogue free of the other family's code.
-template <int S, bool FP16, int TERMS = 0, bool PUR = false>
-__global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
-    constexpr int BLOCKS = 6 * S;                 // 1 KiB blocks per chunk
+// RB: 32-row blocks of the left operand per tile.  RB = 4: 128 x 64 tiles,
+// 8 wavefronts, one workgroup per CU (84 KiB of LDS at S = 7).  RB = 2:
+// 64 x 64 tiles, 4 wavefronts, 56 KiB, two workgroups per CU, so that one
+// tile's pipeline fill and epilogue overlap another's main loop (small
+// matrices, where those are a large share of a tile's time).
+template <int S, bool FP16, int TERMS = 0, bool PUR = false, int RB = 4>
+__global__ __launch_bounds__(128 * RB, RB == 4 ? 1 : 2) void k_ozgemm(GemmParams p) {
+    constexpr int BLOCKS = (RB + 2) * S;          // 1 KiB blocks per chunk
     constexpr int STAGE = BLOCKS * kFragBytes;
-    constexpr int WAVES = kGemmThreads / 64;
+    constexpr int WAVES = 2 * RB;
     constexpr int PER = (BLOCKS + WAVES - 1) / WAVES;  // loads per thread per chunk
     __shared__ __align__(16) uint8_t lds[2][STAGE];
     __shared__ double red[WAVES][kPartials];
@@ -110,7 +115,8 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
     const int64_t a_rb = d.a_rb_stride, b_rb = d.b_rb_stride;
     // Piece i of this thread: block i * WAVES + wave (wave-uniform), lane.
     // Block b of a chunk is digit plane b % S of operand row block b / S (left
-    // operand row blocks 4I..4I+3, then right operand row blocks 2J, 2J+1).
+    // operand row blocks RB I .. RB I + RB - 1, then right operand row blocks
+    // 2J, 2J+1).
     // Loads are buffer loads: one descriptor per piece holding the base of
     // its row block (wave-uniform), the per-chunk offset in a scalar register
     // and the lane's 16 bytes as the only vector offset, so no per-lane
@@ -126,9 +132,9 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
         const int blk = blk0 < BLOCKS ? blk0 : 0;
         const int ob = blk / S;
         poff[i] = (blk % S) * kFragBytes;
-        const uint8_t* base = ob < 4 ? d.pa + int64_t(4 * I + ob) * a_rb
-                                     : d.pb + int64_t(2 * J + ob - 4) * b_rb;
-        const int64_t rb = ob < 4 ? a_rb : b_rb;   // bytes of one row block
+        const uint8_t* base = ob < RB ? d.pa + int64_t(RB * I + ob) * a_rb
+                                      : d.pb + int64_t(2 * J + ob - RB) * b_rb;
+        const int64_t rb = ob < RB ? a_rb : b_rb;   // bytes of one row block
         rsrc[i] = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(base), 0, int(rb),
                                                     kBufferWord3);
     }
@@ -159,7 +165,7 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
 
     auto compute = [&](int buf) __attribute__((always_inline)) {
         const uint8_t* sa = &lds[buf][(wm * S) * kFragBytes + lane * 16];
-        const uint8_t* sb = &lds[buf][((4 + wn) * S) * kFragBytes + lane * 16];
+        const uint8_t* sb = &lds[buf][((RB + wn) * S) * kFragBytes + lane * 16];
         if constexpr (TERMS > 0) {
             const v8h a0 = __builtin_bit_cast(v8h, *reinterpret_cast<const v4i*>(sa));
             const v8h b0 = __builtin_bit_cast(v8h, *reinterpret_cast<const v4i*>(sb));
@@ -244,7 +250,7 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ozgemm(GemmParams p) {
 
     // ---- epilogue -----------------------------------------------------------
     const int col = J * kTileN + wn * 32 + (lane & 31);
-    const int row0 = I * kTileM + wm * 32 + (lane >> 5) * 4;
+    const int row0 = I * (32 * RB) + wm * 32 + (lane >> 5) * 4;
     const int fj = d.eb[col];
     const int mode = p.mode;
     double alpha = 0.0, beta = 0.0, gamma = 0.0;
@@ -425,19 +431,25 @@ static bool purification_mode(int mode) {
 }
 
 template <int S>
-static void launch_s(bool fp16, const GemmParams& p, int ntiles, hipStream_t stream) {
+static void launch_s(bool fp16, const GemmParams& p, int ntiles, int rb, hipStream_t stream) {
     const bool pur = purification_mode(p.mode);
-    if (fp16 && pur)
+    if (pur && rb == 2) {
+        if (fp16)
+            k_ozgemm<S, true, 0, true, 2><<<ntiles, 256, 0, stream>>>(p);
+        else
+            k_ozgemm<S, false, 0, true, 2><<<ntiles, 256, 0, stream>>>(p);
+    } else if (fp16 && pur) {
         k_ozgemm<S, true, 0, true><<<ntiles, kGemmThreads, 0, stream>>>(p);
-    else if (fp16)
+    } else if (fp16) {
         k_ozgemm<S, true, 0, false><<<ntiles, kGemmThreads, 0, stream>>>(p);
-    else if (pur)
+    } else if (pur) {
         k_ozgemm<S, false, 0, true><<<ntiles, kGemmThreads, 0, stream>>>(p);
-    else
+    } else {
         k_ozgemm<S, false, 0, false><<<ntiles, kGemmThreads, 0, stream>>>(p);
+    }
 }
 
-using GemmFn = void (*)(bool, const GemmParams&, int, hipStream_t);
+using GemmFn = void (*)(bool, const GemmParams&, int, int, hipStream_t);
 static const GemmFn kGemm[kMaxSlices + 1] = {
     nullptr,     launch_s<1>, launch_s<2>, launch_s<3>,  launch_s<4>,  launch_s<5>, launch_s<6>,
     launch_s<7>, launch_s<8>, launch_s<9>, launch_s<10>, launch_s<11>, launch_s<12>};
@@ -454,12 +466,17 @@ using TermsFn = void (*)(const GemmParams&, int, hipStream_t);
 static const TermsFn kTerms[kMaxTerms + 1] = {nullptr, launch_terms<1>, launch_terms<2>,
                                               launch_terms<3>, launch_terms<4>};
 
-int launch_ozgemm(int S, dmp_kind kind, const GemmParams& p, int ntiles, hipStream_t stream) {
+int launch_ozgemm(int S, dmp_kind kind, const GemmParams& p, int ntiles, hipStream_t stream,
+                  int rb) {
     if (ntiles <= 0) return DMP_OK;
+    if (rb != 4 && (rb != 2 || kind == DMP_MARKIDIS_FP16 || !purification_mode(p.mode))) {
+        set_error("64-row tiles exist for the Ozaki purification products only");
+        return DMP_EINVAL;
+    }
     if (kind == DMP_MARKIDIS_FP16)
         kTerms[S](p, ntiles, stream);
     else
-        kGemm[S](kind == DMP_OZ_FP16, p, ntiles, stream);
+        kGemm[S](kind == DMP_OZ_FP16, p, ntiles, rb, stream);
     DMP_CHECK_HIP(hipGetLastError());
     return DMP_OK;
 }

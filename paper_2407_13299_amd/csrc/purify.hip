@@ -533,6 +533,22 @@ int e0_blocks() { return kE0Blocks; }
 // ---------------------------------------------------------------------------
 // Host driver.
 
+// Tile height of the Ozaki purification products: 64-row tiles (two
+// workgroups per CU; see the slice GEMM) for S <= 7, measured faster than
+// 128-row tiles from n = 512 to n = 8192 except near n = 1536, where 156
+// 128-row tiles fill one round of the 256 CUs exactly and 300 64-row tiles
+// do not.  Beyond S = 7 two 64-row workgroups no longer fit a CU without
+// spills.  DMP_TILE_ROWS = 64 or 128 forces one height where both exist
+// (for measurements).  A function of (kind, S, n) only, so a matrix gets the
+// same tiles, hence bit-identical results, alone, in a batch or in the tape.
+int tile_blocks_for(dmp_kind kind, int S, int n) {
+    (void)n;
+    if ((kind != DMP_OZ_INT8 && kind != DMP_OZ_FP16) || S > 7) return 4;
+    const char* e = std::getenv("DMP_TILE_ROWS");
+    if (e && std::strcmp(e, "128") == 0) return 4;
+    return 2;
+}
+
 namespace {
 
 struct MatLayout {
@@ -556,7 +572,9 @@ int native_pairs(int n) {
     const int t = (n + 31) / 32;
     return t * (t + 1) / 2;
 }
-int oz_tiles(int n) { return upper_tile_count(n); }
+int oz_tiles(int n, int rb) { return upper_tile_count(n, 32 * rb); }
+
+
 
 MatLayout carve_matrix(Carver& c, int n, int S, dmp_kind kind) {
     MatLayout m{};
@@ -600,6 +618,7 @@ struct GroupPlan {
     int ntiles = 0, units_rowmax = 0, units_digits = 0, max_n = 0;
     int2* pairs = nullptr;            // 32 x 32 tile pairs I <= J of the largest matrix
     int max_pairs = 0;
+    int rb = 4;                       // 32-row blocks per slice-GEMM tile (4 or 2)
 };
 
 size_t carve_group(Carver& c, GroupPlan& g, const int* n) {
@@ -612,7 +631,7 @@ size_t carve_group(Carver& c, GroupPlan& g, const int* n) {
         if (g.kind == DMP_FP64_NATIVE)
             parts = std::max<size_t>(parts, std::max(native_blocks(nb), native_pairs(nb)));
         else
-            parts += size_t(oz_tiles(nb));
+            parts += size_t(oz_tiles(nb, g.rb));
         g.max_pairs = std::max(g.max_pairs, native_pairs(nb));
     }
     // the refinement step reuses the partials of one matrix's tile pairs
@@ -656,9 +675,10 @@ int upload_group(GroupPlan& g, const double* const* H, double* const* P, const i
         for (int b : order) {
             const int nb = n[g.idx[b]];
             part_begin[b] = pbeg;
-            pbeg += oz_tiles(nb);
+            pbeg += oz_tiles(nb, g.rb);
             part_end[b] = pbeg;
-            append_tiles(tiles, tile_rows(nb), tile_cols(nb), true, uint32_t(b));
+            append_tiles(tiles, tile_rows(nb, 32 * g.rb), tile_cols(nb), true, uint32_t(b),
+                         32 * g.rb);
         }
     }
     for (int b = 0; b < cnt; ++b) {
@@ -828,7 +848,7 @@ int timed_gemm(GroupPlan& g, const GemmParams& p, int which, double ops, hipStre
         DMP_CHECK_HIP(hipEventCreate(&t.stop));
         DMP_CHECK_HIP(hipEventRecord(t.start, s));
     }
-    DMP_CHECK(launch_ozgemm(g.S, g.kind, q, g.ntiles, s));
+    DMP_CHECK(launch_ozgemm(g.S, g.kind, q, g.ntiles, s, g.rb));
     if (timers) {
         DMP_CHECK_HIP(hipEventRecord(t.stop, s));
         t.which = which;
@@ -1104,19 +1124,23 @@ int purify_many(int count, const double* const* H, const int* n, const int* nocc
                 const int* slices, dmp_kind kind, int max_iter, int method, int flags,
                 double* const* P, double* E, dmp_info* info, void* ws, size_t ws_bytes,
                 hipStream_t s, size_t* need_out) {
-    // partition by slice count
+    // partition by slice count and tile height (the height follows from each
+    // matrix's own n and S, so a matrix gets the same tiles, hence the same
+    // fixed-order trace sums and bit-identical results, alone or in a batch)
     std::vector<GroupPlan> groups;
     for (int b = 0; b < count; ++b) {
         const int S = kind == DMP_FP64_NATIVE ? 0 : slices[b];
+        const int rb = tile_blocks_for(kind, S, n[b]);
         GroupPlan* g = nullptr;
         for (auto& x : groups)
-            if (x.S == S && kind != DMP_FP64_NATIVE) g = &x;
+            if (x.S == S && x.rb == rb && kind != DMP_FP64_NATIVE) g = &x;
         if (!g) {
             groups.emplace_back();
             g = &groups.back();
             g->S = S;
             g->kind = kind;
             g->method = method;
+            g->rb = rb;
         }
         g->idx.push_back(b);
         g->count++;
