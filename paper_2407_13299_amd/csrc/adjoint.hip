@@ -54,13 +54,11 @@ struct OzCtx {
     double* scal = nullptr;     // [8] device scalars
     PurDesc* pd = nullptr;
     DevState* st = nullptr;
-    const Tile* tiles_up = nullptr;     // 128-row upper tiles (symmetric store)
-    int nt_up = 0;
+    int rb = 4;                         // tile height, as dmp_purify uses for this
+    const Tile* tiles_up = nullptr;     // n and S (upper tiles: purification
+    int nt_up = 0;                      // products and the symmetric store)
     const Tile* tiles_full = nullptr;
     int nt_full = 0;
-    int rb = 4;                         // purification products: the same tiles
-    const Tile* tiles_pur = nullptr;    // as dmp_purify uses for this n and S
-    int nt_pur = 0;
 };
 
 void carve_ctx(Carver& c, OzCtx& x, int n, int S, dmp_kind kind) {
@@ -89,13 +87,12 @@ void carve_ctx(Carver& c, OzCtx& x, int n, int S, dmp_kind kind) {
 
 int bind_ctx(OzCtx& x, const double* H, int nocc, double* P0, hipStream_t s) {
     x.H = H;
-    const int tm = tile_rows(x.n), tn = tile_cols(x.n);
-    DMP_CHECK(cached_tiles(tm, tn, true, &x.tiles_up));
-    DMP_CHECK(cached_tiles(tm, tn, false, &x.tiles_full));
-    x.nt_up = upper_tile_count(x.n);
+    const int TM = 32 * x.rb;
+    const int tm = tile_rows(x.n, TM), tn = tile_cols(x.n);
+    DMP_CHECK(cached_tiles(tm, tn, true, &x.tiles_up, TM));
+    DMP_CHECK(cached_tiles(tm, tn, false, &x.tiles_full, TM));
+    x.nt_up = upper_tile_count(x.n, TM);
     x.nt_full = tm * tn;
-    DMP_CHECK(cached_tiles(tile_rows(x.n, 32 * x.rb), tn, true, &x.tiles_pur, 32 * x.rb));
-    x.nt_pur = upper_tile_count(x.n, 32 * x.rb);
     PurDesc d{};
     d.H = H;
     d.Pb[0] = P0;
@@ -107,7 +104,7 @@ int bind_ctx(OzCtx& x, const double* H, int nocc, double* P0, hipStream_t s) {
     d.n = x.n;
     d.nocc = nocc;
     d.part_begin = 0;
-    d.part_end = x.nt_pur;
+    d.part_end = x.nt_up;
     DMP_CHECK_HIP(hipMemcpyAsync(x.pd, &d, sizeof(d), hipMemcpyHostToDevice, s));
     DMP_CHECK_HIP(hipStreamSynchronize(s));
     return DMP_OK;
@@ -153,13 +150,13 @@ int forward_iteration(const OzCtx& x, const double* P_in, double* X2_out, double
                       bool finalize, hipStream_t s) {
     DMP_CHECK(launch_split(split_of(x, P_in, false, x.ma, x.ea, x.pa, 0), x.S, x.kind, x.st, s));
     GemmParams p{};
-    p.tiles = x.tiles_pur;
+    p.tiles = x.tiles_up;
     p.one = gemm_desc(x, x.pa, x.ea, x.pa, x.ea, X2_out);
     p.one.P = P_in;
     p.partials = x.partials;
     p.states = x.st;
     p.mode = EPI_SQUARE;
-    DMP_CHECK(launch_ozgemm(x.S, x.kind, p, x.nt_pur, s, x.rb));
+    DMP_CHECK(launch_ozgemm(x.S, x.kind, p, x.nt_up, s, x.rb));
     DMP_CHECK(launch_finalize_coef(x.pd, x.st, 1, s));
     DMP_CHECK(launch_split(split_of(x, X2_out, false, x.mb, x.eb, x.pb, 0), x.S, x.kind, x.st, s));
     p.one = gemm_desc(x, x.pb, x.eb, x.pa, x.ea, P_out);
@@ -167,7 +164,7 @@ int forward_iteration(const OzCtx& x, const double* P_in, double* X2_out, double
     p.one.X2 = X2_out;
     p.one.H = x.H;
     p.mode = EPI_UPDATE;
-    DMP_CHECK(launch_ozgemm(x.S, x.kind, p, x.nt_pur, s, x.rb));
+    DMP_CHECK(launch_ozgemm(x.S, x.kind, p, x.nt_up, s, x.rb));
     if (finalize) DMP_CHECK(launch_finalize_iter(x.pd, x.st, 1, s));
     return DMP_OK;
 }
@@ -186,7 +183,7 @@ int gemm_store(const OzCtx& x, const uint8_t* pa, const int* ea, const uint8_t* 
     p.one.rowmax = rowmax;
     p.one.colmax = colmax;
     p.mode = sym ? EPI_STORE_SYM : EPI_STORE;
-    return launch_ozgemm(x.S, x.kind, p, sym ? x.nt_up : x.nt_full, s);
+    return launch_ozgemm(x.S, x.kind, p, sym ? x.nt_up : x.nt_full, s, x.rb);
 }
 
 __device__ inline double wsum(double v) {

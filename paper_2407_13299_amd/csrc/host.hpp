@@ -62,12 +62,14 @@ int split_units_rowmax(int R);
 int split_units_digits(int R, int KC);
 
 struct GemmParams;
-// 32-row blocks per slice-GEMM tile of an n x n Ozaki purification product
-// (2: 64-row tiles for small n, else 4); a function of (kind, S, n) only
+// 32-row blocks per slice-GEMM tile (2: 64-row tiles, 4: 128-row tiles) of
+// the products of an n x n Ozaki purification (and of its adjoint); a
+// function of (kind, S, n) only.  The general GEMM entry points keep 128-row
+// tiles, which measured faster on dense random operands.
 int tile_blocks_for(dmp_kind kind, int S, int n);
 
 // rb: 32-row blocks per tile of the left operand (4, or 2 for the 64-row
-// variant of the Ozaki purification products)
+// variant: Ozaki kinds, S <= 7)
 int launch_ozgemm(int S, dmp_kind kind, const GemmParams& p, int ntiles, hipStream_t stream,
                   int rb = 4);
 

@@ -433,12 +433,20 @@ static bool purification_mode(int mode) {
 template <int S>
 static void launch_s(bool fp16, const GemmParams& p, int ntiles, int rb, hipStream_t stream) {
     const bool pur = purification_mode(p.mode);
-    if (pur && rb == 2) {
-        if (fp16)
-            k_ozgemm<S, true, 0, true, 2><<<ntiles, 256, 0, stream>>>(p);
-        else
-            k_ozgemm<S, false, 0, true, 2><<<ntiles, 256, 0, stream>>>(p);
-    } else if (fp16 && pur) {
+    if constexpr (S <= 7) {   // the 64-row variant exists up to S = 7
+        if (rb == 2) {
+            if (fp16 && pur)
+                k_ozgemm<S, true, 0, true, 2><<<ntiles, 256, 0, stream>>>(p);
+            else if (fp16)
+                k_ozgemm<S, true, 0, false, 2><<<ntiles, 256, 0, stream>>>(p);
+            else if (pur)
+                k_ozgemm<S, false, 0, true, 2><<<ntiles, 256, 0, stream>>>(p);
+            else
+                k_ozgemm<S, false, 0, false, 2><<<ntiles, 256, 0, stream>>>(p);
+            return;
+        }
+    }
+    if (fp16 && pur) {
         k_ozgemm<S, true, 0, true><<<ntiles, kGemmThreads, 0, stream>>>(p);
     } else if (fp16) {
         k_ozgemm<S, true, 0, false><<<ntiles, kGemmThreads, 0, stream>>>(p);
@@ -469,8 +477,8 @@ static const TermsFn kTerms[kMaxTerms + 1] = {nullptr, launch_terms<1>, launch_t
 int launch_ozgemm(int S, dmp_kind kind, const GemmParams& p, int ntiles, hipStream_t stream,
                   int rb) {
     if (ntiles <= 0) return DMP_OK;
-    if (rb != 4 && (rb != 2 || kind == DMP_MARKIDIS_FP16 || !purification_mode(p.mode))) {
-        set_error("64-row tiles exist for the Ozaki purification products only");
+    if (rb != 4 && (rb != 2 || kind == DMP_MARKIDIS_FP16 || S > 7)) {
+        set_error("64-row tiles exist for the Ozaki kinds with S <= 7 only");
         return DMP_EINVAL;
     }
     if (kind == DMP_MARKIDIS_FP16)
