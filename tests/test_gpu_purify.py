@@ -234,3 +234,20 @@ def test_side_stream_and_concurrent_threads():
     assert not errors, errors
     for i in range(2):
         assert np.array_equal(out[i][0], ref[i][0]) and out[i][1] == ref[i][1]
+
+
+@pytest.mark.parametrize("method", ["canonical", "trs4"])
+def test_both_tile_heights_match_the_oracle(method, monkeypatch):
+    """The purification products run on 64-row tiles for S <= 7 and on 128-row
+    tiles otherwise; DMP_TILE_ROWS=128 forces the 128-row kernel.  Both reach
+    the projector; they differ only in the fixed order of the trace sums."""
+    h, _, _ = spectrum_hamiltonian(300, 150, seed=9)
+    p_ref, e_ref, _, _ = projector.eigh_projector(h, 150)
+    out = {}
+    for rows in ("64", "128"):
+        monkeypatch.setenv("DMP_TILE_ROWS", rows)
+        p, e, info = gpu_purify(h, 150, tol=1e-12, slices=7, kind="int8", method=method)
+        assert info["stop"] == "converged"
+        assert np.max(np.abs(p - p_ref)) < TOL_P and abs(e - e_ref) < TOL_E
+        out[rows] = p
+    assert np.max(np.abs(out["64"] - out["128"])) < 1e-12
