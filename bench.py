@@ -54,11 +54,19 @@ def parse():
     return ap.parse_args()
 
 
+def kernel_code_digest(path):
+    """SHA-256 of a kernel source with its // comments and all whitespace
+    removed: it changes with the code, not with the comments."""
+    import hashlib
+    import re
+    text = re.sub(r"//[^\n]*", "", open(path).read())
+    return hashlib.sha256(re.sub(r"\s+", "", text).encode()).hexdigest()
+
+
 def profiled_traffic(kind, slices, which="update"):
     """HBM bytes per launch of the slice GEMM from the committed rocprofv3
     counter summary, or None when that summary was taken on another version
-    of the kernel source (or for another configuration)."""
-    import hashlib
+    of the kernel code (or for another configuration)."""
     path = os.path.join(ROOT, "profiles", f"k_ozgemm_{kind}_s{slices}_tb8192_traffic.md")
     src = os.path.join(ROOT, "paper_2407_13299_amd", "csrc", "ozgemm.hip")
     if not os.path.exists(path):
@@ -68,8 +76,7 @@ def profiled_traffic(kind, slices, which="update"):
         if " = " in line:
             k, v = line.split(" = ", 1)
             vals[k.strip()] = v.strip()
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if vals.get("source_sha256") != digest:
+    if vals.get("code_sha256") != kernel_code_digest(src):
         return None
     v = vals.get(f"{which}_traffic_bytes")
     return float(v) if v is not None else None

@@ -2,10 +2,11 @@
 // with the FP64 summation and the purification work fused into the epilogue.
 //
 // A workgroup of 8 wavefronts owns one 128 x 64 output tile (4 x 2 quadrants
-// of 32 x 32, one per wavefront).  The reduction runs in chunks (32 INT8 or
-// 16 FP16 elements); one chunk of the tile is 6 S fragment blocks of 1 KiB
-// (4 row blocks of the left operand, 2 of the right, S digit planes each),
-// contiguous in HBM per row block.  Loads run two chunks ahead of the MFMA
+// of 32 x 32, one per wavefront), or, in the 64-row variant, 4 wavefronts own
+// a 64 x 64 tile (see RB below).  The reduction runs in chunks (32 INT8 or
+// 16 FP16 elements); one chunk of a 128 x 64 tile is 6 S fragment blocks of
+// 1 KiB (4 row blocks of the left operand, 2 of the right, S digit planes
+// each; 4 S for 64 x 64), contiguous in HBM per row block.  Loads run two chunks ahead of the MFMA
 // work through two register sets into two LDS buffers, with one barrier per
 // chunk (each step: load chunk c + 2 into the free register set, MFMAs on
 // chunk c from LDS, store chunk c + 1 into the other LDS buffer, barrier).
