@@ -195,6 +195,25 @@ struct GemmParams {
     // nullable (kernel timing): [0] += shader-clock cycles and [1] += 100 MHz
     // real-time ticks of every workgroup, from its start to its end
     unsigned long long* clk;
+    // Reduction split of the last tiles (purification modes; ``fix`` null: no
+    // split).  Blocks [0, nfull) own tiles [0, nfull) whole.  Block nfull + u
+    // owns part u % nsplit of tile nfull + u / nsplit: it reduces the chunks
+    // [KC part / nsplit, KC (part + 1) / nsplit) and stores its INT32 group
+    // sums at piece u of ``fix`` instead of running the epilogue.  The fixup
+    // launch (one block per split tile) adds the parts of its tile (integer
+    // sums: exact in any order) and runs the epilogue.
+    int* fix;
+    int nfull, nsplit;
 };
+
+// Tail split of a slice-GEMM launch: at most kMaxSplit parts per tile, at
+// least kMinSplitChunks reduction chunks per part, at most kMaxPieces parts
+// in all (the capacity of the part buffer).
+constexpr int kMaxSplit = 8;
+constexpr int kMinSplitChunks = 8;
+constexpr int kMaxPieces = 512;
+// INT32 group sums of one part: S accumulators of 16 values per lane of each
+// wavefront.
+inline size_t piece_ints(int S, int rb) { return size_t(2 * rb) * S * 16 * 64; }
 
 }  // namespace dmp

@@ -1,6 +1,7 @@
 // Host-side helpers of libdmp: error text, tile orders, rocBLAS handles.
 #include "host.hpp"
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <map>
@@ -158,6 +159,27 @@ int check_kind_slices(dmp_kind kind, int slices) {
         return DMP_EINVAL;
     }
     return DMP_OK;
+}
+
+static int split_parts_max(int min_kc) { return std::min(kMaxSplit, min_kc / kMinSplitChunks); }
+
+TailSplit plan_tail_split(int ntiles, int slots, int min_kc, int max_pieces) {
+    TailSplit t{ntiles, 1};
+    // with no full round the fixup launch costs more than the parts save
+    if (ntiles <= slots || slots <= 0) return t;
+    const int r = ntiles % slots;
+    if (r == 0) return t;
+    const int parts = std::min({split_parts_max(min_kc), slots / r, max_pieces / r});
+    if (parts < 2) return t;
+    t.nfull = ntiles - r;
+    t.nsplit = parts;
+    return t;
+}
+
+int tail_split_capacity(int ntiles, int min_kc) {
+    const int parts = split_parts_max(min_kc);
+    if (parts < 2 || ntiles <= 0) return 0;
+    return int(std::min<int64_t>(kMaxPieces, int64_t(ntiles) * parts));
 }
 
 int64_t chunks_of(int k, dmp_kind kind) { return round_up(k, kKPad) / chunk_k(kind); }

@@ -72,6 +72,25 @@ int tile_blocks_for(dmp_kind kind, int S, int n);
 // variant: Ozaki kinds, S <= 7)
 int launch_ozgemm(int S, dmp_kind kind, const GemmParams& p, int ntiles, hipStream_t stream,
                   int rb = 4);
+// Workgroups of the purification-mode slice GEMM (kind, S, rb) resident on
+// the current device at once (CUs x workgroups per CU).
+int gemm_slots(int S, dmp_kind kind, int rb, int* slots);
+
+// Tail split of ``ntiles`` tiles of equal cost: tiles [0, nfull) whole, the
+// rest in nsplit parts each (nsplit == 1: no split).
+struct TailSplit {
+    int nfull, nsplit;
+};
+// ``slots`` workgroups run at once, so the tiles run in full rounds and a
+// last round of r = ntiles mod slots tiles that leaves the rest of the chip
+// idle; when there is at least one full round, those r tiles are split into
+// as many parts as fill it (at most
+// kMaxSplit, at least kMinSplitChunks of the ``min_kc`` chunks each, at most
+// ``max_pieces`` parts in all).
+TailSplit plan_tail_split(int ntiles, int slots, int min_kc, int max_pieces);
+// Parts of a tail split a group of ``ntiles`` tiles may need (the size of its
+// part buffer in pieces, 0 when no split can arise).
+int tail_split_capacity(int ntiles, int min_kc);
 
 int native_dsyrk_upper(hipStream_t stream, int n, const double* A, double* C);
 int native_dsyrkx_upper(hipStream_t stream, int n, const double* A, const double* B, double* C);

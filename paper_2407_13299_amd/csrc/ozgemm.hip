@@ -83,7 +83,13 @@ __device__ inline double wave_sum(double v) {
 // 64 x 64 tiles, 4 wavefronts, 56 KiB, two workgroups per CU, so that one
 // tile's pipeline fill and epilogue overlap another's main loop (small
 // matrices, where those are a large share of a tile's time).
-template <int S, bool FP16, int TERMS = 0, bool PUR = false, int RB = 4>
+// PHASE: kWhole for whole tiles; the split tail (GemmParams::fix) adds two
+// launches: kPiece, one block per part (its share of the chunks, group sums
+// stored, no epilogue), then kFixup, one block per split tile (adds the
+// parts' group sums in place of the main loop, then runs the epilogue).
+// Separate instantiations keep the whole-tile kernel's registers as they are.
+constexpr int kWhole = 0, kPiece = 1, kFixup = 2;
+template <int S, bool FP16, int TERMS = 0, bool PUR = false, int RB = 4, int PHASE = kWhole>
 __global__ __launch_bounds__(128 * RB, RB == 4 ? 1 : 2) void k_ozgemm(GemmParams p) {
     constexpr int BLOCKS = (RB + 2) * S;          // 1 KiB blocks per chunk
     constexpr int STAGE = BLOCKS * kFragBytes;
@@ -92,12 +98,21 @@ __global__ __launch_bounds__(128 * RB, RB == 4 ? 1 : 2) void k_ozgemm(GemmParams
     __shared__ __align__(16) uint8_t lds[2][STAGE];
     __shared__ double red[WAVES][kPartials];
 
+    static_assert(PHASE == kWhole || (PUR && TERMS == 0), "tail split: purification modes, Ozaki kinds");
     // XCD-aware block order: the hardware hands consecutive blocks to the 8
     // XCDs in turn; give every XCD one contiguous slice of the tile list.
-    const int nb = gridDim.x, b = blockIdx.x;
-    const int xcd = b & 7, q = nb >> 3, rem = nb & 7, loc = b >> 3;
-    const int t = p.spread ? b
-                           : (xcd < rem) ? xcd * (q + 1) + loc : rem * (q + 1) + (xcd - rem) * q + loc;
+    const int b = blockIdx.x;
+    int t, part = 0;
+    if constexpr (PHASE == kWhole) {
+        const int nb = gridDim.x;
+        const int xcd = b & 7, q = nb >> 3, rem = nb & 7, loc = b >> 3;
+        t = p.spread ? b : (xcd < rem) ? xcd * (q + 1) + loc : rem * (q + 1) + (xcd - rem) * q + loc;
+    } else if constexpr (PHASE == kPiece) {
+        t = p.nfull + b / p.nsplit;
+        part = b - (t - p.nfull) * p.nsplit;
+    } else {
+        t = p.nfull + b;
+    }
     const Tile tile = p.tiles[t];
     const MatDesc d = p.descs ? p.descs[tile.mat] : p.one;
     const DevState* st = p.states ? p.states + d.state_index : nullptr;
@@ -112,7 +127,12 @@ __global__ __launch_bounds__(128 * RB, RB == 4 ? 1 : 2) void k_ozgemm(GemmParams
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
     const int wm = wave >> 1, wn = wave & 1;
     const int I = tile.I, J = tile.J;
-    const int KC = d.KC;
+    // chunks of this block: all of them, or those of its part
+    int KC = d.KC, kbase = 0;
+    if constexpr (PHASE == kPiece) {
+        kbase = int(int64_t(d.KC) * part / p.nsplit);
+        KC = int(int64_t(d.KC) * (part + 1) / p.nsplit) - kbase;
+    }
     const int64_t a_rb = d.a_rb_stride, b_rb = d.b_rb_stride;
     // Piece i of this thread: block i * WAVES + wave (wave-uniform), lane.
     // Block b of a chunk is digit plane b % S of operand row block b / S (left
@@ -132,7 +152,7 @@ __global__ __launch_bounds__(128 * RB, RB == 4 ? 1 : 2) void k_ozgemm(GemmParams
         const int blk0 = i * WAVES + wave;
         const int blk = blk0 < BLOCKS ? blk0 : 0;
         const int ob = blk / S;
-        poff[i] = (blk % S) * kFragBytes;
+        poff[i] = (blk % S) * kFragBytes + kbase * (S * kFragBytes);
         const uint8_t* base = ob < RB ? d.pa + int64_t(RB * I + ob) * a_rb
                                       : d.pb + int64_t(2 * J + ob - RB) * b_rb;
         const int64_t rb = ob < RB ? a_rb : b_rb;   // bytes of one row block
@@ -242,10 +262,54 @@ __global__ __launch_bounds__(128 * RB, RB == 4 ? 1 : 2) void k_ozgemm(GemmParams
     // an update whose product weight is zero (a TRS4 step without the
     // second product) keeps only the elementwise part
     const bool no_product = PUR && p.mode == EPI_UPDATE && st != nullptr && st->gamma == 0.0;
-    if (!no_product) {
-        for (int kc = -2; kc < KC; kc += 2) {
-            step(kc, 0, r0, r1);
-            step(kc + 1, 1, r1, r0);
+    auto add_clock = [&]() __attribute__((always_inline)) {
+        if (clocked) {
+            const uint64_t dc = __builtin_amdgcn_s_memtime() - clk_c;
+            const uint64_t dr = __builtin_amdgcn_s_memrealtime() - clk_r;
+            if (threadIdx.x == 0) {
+                atomicAdd(p.clk + 0, static_cast<unsigned long long>(dc));
+                atomicAdd(p.clk + 1, static_cast<unsigned long long>(dr));
+            }
+        }
+    };
+    // Part u of the split tail keeps its group sums at piece u of p.fix:
+    // [wavefront][group][4 x 4 values][lane], 16 bytes per lane and store.
+    constexpr int64_t kPieceInts = int64_t(WAVES) * S * 16 * 64;
+    if constexpr (PHASE == kFixup) {
+        if (!no_product) {
+            const int* src = p.fix + int64_t(b) * p.nsplit * kPieceInts +
+                             int64_t(wave) * (S * 16 * 64) + lane * 4;
+            for (int pt = 0; pt < p.nsplit; ++pt) {
+#pragma unroll
+                for (int g = 0; g < S; ++g)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const v4i x = *reinterpret_cast<const v4i*>(src + (g * 4 + q) * 256);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) acc[g][4 * q + e] += x[e];
+                    }
+                src += kPieceInts;
+            }
+        }
+    } else {
+        if (!no_product && KC > 0) {
+            for (int kc = -2; kc < KC; kc += 2) {
+                step(kc, 0, r0, r1);
+                step(kc + 1, 1, r1, r0);
+            }
+        }
+        if constexpr (PHASE == kPiece) {
+            if (!no_product) {
+                int* dst = p.fix + int64_t(b) * kPieceInts + int64_t(wave) * (S * 16 * 64) + lane * 4;
+#pragma unroll
+                for (int g = 0; g < S; ++g)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        *reinterpret_cast<v4i*>(dst + (g * 4 + q) * 256) =
+                            v4i{acc[g][4 * q], acc[g][4 * q + 1], acc[g][4 * q + 2], acc[g][4 * q + 3]};
+            }
+            add_clock();
+            return;
         }
     }
 
@@ -417,51 +481,73 @@ __global__ __launch_bounds__(128 * RB, RB == 4 ? 1 : 2) void k_ozgemm(GemmParams
             p.partials[int64_t(t) * kPartials + 1] = r1;
         }
     }
-    if (clocked) {
-        const uint64_t dc = __builtin_amdgcn_s_memtime() - clk_c;
-        const uint64_t dr = __builtin_amdgcn_s_memrealtime() - clk_r;
-        if (threadIdx.x == 0) {
-            atomicAdd(p.clk + 0, static_cast<unsigned long long>(dc));
-            atomicAdd(p.clk + 1, static_cast<unsigned long long>(dr));
-        }
-    }
+    add_clock();
 }
 
 static bool purification_mode(int mode) {
     return mode == EPI_SQUARE || mode == EPI_UPDATE || mode == EPI_SQUARE_TRS4;
 }
 
-template <int S>
+template <int S, int PHASE>
 static void launch_s(bool fp16, const GemmParams& p, int ntiles, int rb, hipStream_t stream) {
     const bool pur = purification_mode(p.mode);
     if constexpr (S <= 7) {   // the 64-row variant exists up to S = 7
         if (rb == 2) {
             if (fp16 && pur)
-                k_ozgemm<S, true, 0, true, 2><<<ntiles, 256, 0, stream>>>(p);
-            else if (fp16)
-                k_ozgemm<S, true, 0, false, 2><<<ntiles, 256, 0, stream>>>(p);
+                k_ozgemm<S, true, 0, true, 2, PHASE><<<ntiles, 256, 0, stream>>>(p);
             else if (pur)
-                k_ozgemm<S, false, 0, true, 2><<<ntiles, 256, 0, stream>>>(p);
-            else
-                k_ozgemm<S, false, 0, false, 2><<<ntiles, 256, 0, stream>>>(p);
+                k_ozgemm<S, false, 0, true, 2, PHASE><<<ntiles, 256, 0, stream>>>(p);
+            else if constexpr (PHASE == kWhole) {
+                if (fp16)
+                    k_ozgemm<S, true, 0, false, 2><<<ntiles, 256, 0, stream>>>(p);
+                else
+                    k_ozgemm<S, false, 0, false, 2><<<ntiles, 256, 0, stream>>>(p);
+            }
             return;
         }
     }
     if (fp16 && pur) {
-        k_ozgemm<S, true, 0, true><<<ntiles, kGemmThreads, 0, stream>>>(p);
-    } else if (fp16) {
-        k_ozgemm<S, true, 0, false><<<ntiles, kGemmThreads, 0, stream>>>(p);
+        k_ozgemm<S, true, 0, true, 4, PHASE><<<ntiles, kGemmThreads, 0, stream>>>(p);
     } else if (pur) {
-        k_ozgemm<S, false, 0, true><<<ntiles, kGemmThreads, 0, stream>>>(p);
-    } else {
-        k_ozgemm<S, false, 0, false><<<ntiles, kGemmThreads, 0, stream>>>(p);
+        k_ozgemm<S, false, 0, true, 4, PHASE><<<ntiles, kGemmThreads, 0, stream>>>(p);
+    } else if constexpr (PHASE == kWhole) {
+        if (fp16)
+            k_ozgemm<S, true, 0, false><<<ntiles, kGemmThreads, 0, stream>>>(p);
+        else
+            k_ozgemm<S, false, 0, false><<<ntiles, kGemmThreads, 0, stream>>>(p);
     }
 }
 
+// Workgroups of the purification-mode slice GEMM resident per CU.
+template <int S>
+static int resident_s(bool fp16, int rb, int* per_cu) {
+    hipError_t e;
+    if constexpr (S <= 7) {
+        if (rb == 2) {
+            e = fp16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_ozgemm<S, true, 0, true, 2>, 256, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_ozgemm<S, false, 0, true, 2>, 256, 0);
+            return e == hipSuccess ? DMP_OK : DMP_EHIP;
+        }
+    }
+    e = fp16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_ozgemm<S, true, 0, true>, kGemmThreads, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_ozgemm<S, false, 0, true>, kGemmThreads, 0);
+    return e == hipSuccess ? DMP_OK : DMP_EHIP;
+}
+
 using GemmFn = void (*)(bool, const GemmParams&, int, int, hipStream_t);
-static const GemmFn kGemm[kMaxSlices + 1] = {
-    nullptr,     launch_s<1>, launch_s<2>, launch_s<3>,  launch_s<4>,  launch_s<5>, launch_s<6>,
-    launch_s<7>, launch_s<8>, launch_s<9>, launch_s<10>, launch_s<11>, launch_s<12>};
+#define DMP_GEMM_TABLE(PH)                                                                    \
+    {nullptr,          launch_s<1, PH>,  launch_s<2, PH>,  launch_s<3, PH>,  launch_s<4, PH>,   \
+     launch_s<5, PH>,  launch_s<6, PH>,  launch_s<7, PH>,  launch_s<8, PH>,  launch_s<9, PH>,   \
+     launch_s<10, PH>, launch_s<11, PH>, launch_s<12, PH>}
+static const GemmFn kGemm[3][kMaxSlices + 1] = {DMP_GEMM_TABLE(kWhole), DMP_GEMM_TABLE(kPiece),
+                                                DMP_GEMM_TABLE(kFixup)};
+#undef DMP_GEMM_TABLE
+
+using ResidentFn = int (*)(bool, int, int*);
+static const ResidentFn kResident[kMaxSlices + 1] = {
+    nullptr,        resident_s<1>, resident_s<2>,  resident_s<3>,  resident_s<4>,
+    resident_s<5>,  resident_s<6>, resident_s<7>,  resident_s<8>,  resident_s<9>,
+    resident_s<10>, resident_s<11>, resident_s<12>};
 
 template <int T>
 static void launch_terms(const GemmParams& p, int ntiles, hipStream_t stream) {
@@ -482,11 +568,45 @@ int launch_ozgemm(int S, dmp_kind kind, const GemmParams& p, int ntiles, hipStre
         set_error("64-row tiles exist for the Ozaki kinds with S <= 7 only");
         return DMP_EINVAL;
     }
+    if (p.fix != nullptr) {
+        const int tail = ntiles - p.nfull;
+        if (kind == DMP_MARKIDIS_FP16 || !purification_mode(p.mode) || p.nfull < 0 || tail < 1 ||
+            p.nsplit < 2 || int64_t(tail) * p.nsplit > kMaxPieces) {
+            set_error("invalid tail split (nfull %d of %d tiles, %d parts)", p.nfull, ntiles, p.nsplit);
+            return DMP_EINVAL;
+        }
+        // whole tiles (full rounds), the parts, then the fixup; each launch
+        // starts when the previous one has ended (same stream)
+        const bool fp16 = kind == DMP_OZ_FP16;
+        if (p.nfull > 0) kGemm[kWhole][S](fp16, p, p.nfull, rb, stream);
+        kGemm[kPiece][S](fp16, p, tail * p.nsplit, rb, stream);
+        kGemm[kFixup][S](fp16, p, tail, rb, stream);
+        DMP_CHECK_HIP(hipGetLastError());
+        return DMP_OK;
+    }
     if (kind == DMP_MARKIDIS_FP16)
         kTerms[S](p, ntiles, stream);
     else
-        kGemm[S](kind == DMP_OZ_FP16, p, ntiles, rb, stream);
+        kGemm[kWhole][S](kind == DMP_OZ_FP16, p, ntiles, rb, stream);
     DMP_CHECK_HIP(hipGetLastError());
+    return DMP_OK;
+}
+
+int gemm_slots(int S, dmp_kind kind, int rb, int* slots) {
+    *slots = 0;
+    if ((kind != DMP_OZ_INT8 && kind != DMP_OZ_FP16) || S < 1 || S > kMaxSlices ||
+        (rb == 2 && S > 7) || (rb != 2 && rb != 4)) {
+        set_error("no slice GEMM for this kind, S and tile height");
+        return DMP_EINVAL;
+    }
+    int dev = 0, cus = 0, per_cu = 0;
+    DMP_CHECK_HIP(hipGetDevice(&dev));
+    DMP_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (kResident[S](kind == DMP_OZ_FP16, rb, &per_cu) != DMP_OK) {
+        set_error("occupancy query of the slice GEMM failed");
+        return DMP_EHIP;
+    }
+    *slots = cus * per_cu;
     return DMP_OK;
 }
 

@@ -598,6 +598,12 @@ MatLayout carve_matrix(Carver& c, int n, int S, dmp_kind kind) {
     return m;
 }
 
+// DMP_TAIL_SPLIT = 0 keeps every tile whole (for measurements).
+bool tail_split_enabled() {
+    const char* e = std::getenv("DMP_TAIL_SPLIT");
+    return !(e && std::strcmp(e, "0") == 0);
+}
+
 // Everything a group of matrices (same S and kind) needs on the device.
 struct GroupPlan {
     int count = 0;
@@ -619,21 +625,35 @@ struct GroupPlan {
     int2* pairs = nullptr;            // 32 x 32 tile pairs I <= J of the largest matrix
     int max_pairs = 0;
     int rb = 4;                       // 32-row blocks per slice-GEMM tile (4 or 2)
+    int* fix = nullptr;               // part buffer of the tail split
+    int fix_pieces = 0;               // its capacity in parts
+    int min_kc = 0, max_kc = 0;       // fewest / most reduction chunks of a matrix
+    TailSplit tail{0, 1};             // tail split of the slice GEMMs
 };
 
 size_t carve_group(Carver& c, GroupPlan& g, const int* n) {
     size_t parts = 0;
     g.lay.resize(g.count);
     g.max_pairs = 1;
+    g.min_kc = g.max_kc = 0;
     for (int b = 0; b < g.count; ++b) {
         const int nb = n[g.idx[b]];
         g.lay[b] = carve_matrix(c, nb, g.S, g.kind);
-        if (g.kind == DMP_FP64_NATIVE)
+        if (g.kind == DMP_FP64_NATIVE) {
             parts = std::max<size_t>(parts, std::max(native_blocks(nb), native_pairs(nb)));
-        else
+        } else {
             parts += size_t(oz_tiles(nb, g.rb));
+            const int kc = int(chunks_of(nb, g.kind));
+            g.min_kc = b == 0 ? kc : std::min(g.min_kc, kc);
+            g.max_kc = std::max(g.max_kc, kc);
+        }
         g.max_pairs = std::max(g.max_pairs, native_pairs(nb));
     }
+    // part buffer of the tail split (Ozaki kinds), sized for the largest
+    // matrix, so that a batch needs no less workspace than any of its members
+    g.fix_pieces = (g.kind == DMP_OZ_INT8 || g.kind == DMP_OZ_FP16)
+                       ? tail_split_capacity(int(parts), g.max_kc) : 0;
+    g.fix = g.fix_pieces > 0 ? c.take<int>(size_t(g.fix_pieces) * piece_ints(g.S, g.rb)) : nullptr;
     // the refinement step reuses the partials of one matrix's tile pairs
     parts = std::max<size_t>(parts, size_t(g.max_pairs));
     g.pd = c.take<PurDesc>(g.count);
@@ -782,6 +802,12 @@ int upload_group(GroupPlan& g, const double* const* H, double* const* P, const i
         u1[b] = md;
     }
     g.ntiles = int(tiles.size());
+    g.tail = TailSplit{g.ntiles, 1};
+    if (g.fix != nullptr && tail_split_enabled()) {
+        int slots = 0;
+        DMP_CHECK(gemm_slots(g.S, g.kind, g.rb, &slots));
+        g.tail = plan_tail_split(g.ntiles, slots, g.min_kc, g.fix_pieces);
+    }
     g.units_rowmax = urow;
     g.units_digits = udig;
     auto up = [&](void* dst, const void* src, size_t bytes) -> int {
@@ -871,6 +897,11 @@ int launch_oz_iteration(GroupPlan& g, int par, hipStream_t s,
     const bool trs4 = g.method == DMP_TRS4;
     p.mode = trs4 ? EPI_SQUARE_TRS4 : EPI_SQUARE;
     p.spread = g.count > 1 ? 1 : 0;
+    if (g.tail.nsplit > 1) {
+        p.fix = g.fix;
+        p.nfull = g.tail.nfull;
+        p.nsplit = g.tail.nsplit;
+    }
     DMP_CHECK(timed_gemm(g, p, 0, ops, s, timers));
     if (trs4)
         k_finalize_trs4<<<g.count, 256, 0, s>>>(g.pd, g.st);

@@ -56,7 +56,12 @@ def test_workspace_queries(lib):
     assert m1 == lib.dmp_gemm_workspace_bytes(100, 70, 130, 2, 2)
     assert lib.dmp_gemm_workspace_bytes(100, 70, 130, 5, 3) == 0
     assert lib.dmp_purify_workspace_bytes(512, 5, 3) == 0
-    assert lib.dmp_purify_workspace_bytes(512, 3, 3) == lib.dmp_purify_workspace_bytes(512, 2, 2)
+    # Markidis purification: one workspace for any number of terms (two FP16
+    # planes), no larger than FP16 S = 2, which also holds the part buffer of
+    # the split tail
+    w = lib.dmp_purify_workspace_bytes(512, 3, 3)
+    assert w == lib.dmp_purify_workspace_bytes(512, 1, 3)
+    assert 0 < w <= lib.dmp_purify_workspace_bytes(512, 2, 2)
     n = (ctypes.c_int * 3)(128, 300, 1536)
     assert lib.dmp_purify_batched_workspace_bytes(3, n, 7, 1) > lib.dmp_purify_workspace_bytes(1536, 7, 1)
 

@@ -251,3 +251,53 @@ def test_both_tile_heights_match_the_oracle(method, monkeypatch):
         assert np.max(np.abs(p - p_ref)) < TOL_P and abs(e - e_ref) < TOL_E
         out[rows] = p
     assert np.max(np.abs(out["64"] - out["128"])) < 1e-12
+
+
+def _split_case(name):
+    # more tiles than fit the chip at once (512 of 64 x 64 or 256 of 128 x 64
+    # on 256 CUs), so the last round is split: 528 / 561 tiles of 64 x 64,
+    # 272 of 128 x 64 (S = 8) at n = 2048 / 2100
+    if name == "tb2048":
+        return tight_binding_hamiltonian(8, 8, 8, seed=1), 512
+    n = int(name[2:])
+    h, _, _ = spectrum_hamiltonian(n, n // 2, seed=31)
+    return h, n // 2
+
+
+@pytest.mark.parametrize("method,kind,s,case", [
+    ("canonical", "int8", 7, "tb2048"), ("trs4", "int8", 7, "tb2048"),
+    ("canonical", "fp16", 7, "sp2100"), ("canonical", "int8", 8, "tb2048"),
+    ("canonical", "fp16", 5, "sp2100")])
+def test_split_tail_is_bit_identical(method, kind, s, case, monkeypatch):
+    """The tiles of a slice GEMM's last, partly filled round run in parts
+    along the reduction, whose INT32 group sums a fixup launch adds: the same
+    integers, hence the same P, E, iteration count and stop as whole tiles
+    (DMP_TAIL_SPLIT=0); with S >= 7, within the tolerance of the projector
+    (S = 5 stagnates short of it, split or not)."""
+    h, nocc = _split_case(case)
+    out = {}
+    for split in ("1", "0"):
+        monkeypatch.setenv("DMP_TAIL_SPLIT", split)
+        out[split] = gpu_purify(h, nocc, tol=1e-10, slices=s, kind=kind, method=method)
+    (p1, e1, i1), (p0, e0, i0) = out["1"], out["0"]
+    assert i1["stop"] == i0["stop"] and i1["iters"] == i0["iters"]
+    assert np.array_equal(p1, p0) and e1 == e0
+    if s >= 7:
+        p_ref, e_ref, _, _ = projector.eigh_projector(h, nocc)
+        assert i1["stop"] == "converged"
+        assert np.max(np.abs(p1 - p_ref)) < TOL_P and abs(e1 - e_ref) < TOL_E
+
+
+def test_split_tail_in_a_batch(monkeypatch):
+    """A batch whose tail tiles are split equals its members run alone with
+    whole tiles, bit for bit."""
+    cases = [_split_case("tb2048"), _split_case("sp1100")]   # 699 tiles
+    monkeypatch.setenv("DMP_TAIL_SPLIT", "1")
+    ps, es, infos = dmp.purify_batched([dev(h) for h, _ in cases], [k for _, k in cases],
+                                       tol=1e-10, slices=7)
+    torch.cuda.synchronize()
+    monkeypatch.setenv("DMP_TAIL_SPLIT", "0")
+    for (h, nocc), p, e, info in zip(cases, ps, es, infos):
+        p0, e0, i0 = gpu_purify(h, nocc, tol=1e-10, slices=7)
+        assert info["iters"] == i0["iters"]
+        assert np.array_equal(p.cpu().numpy(), p0) and e == e0
