@@ -82,6 +82,19 @@ def profiled_traffic(kind, slices, which="update"):
     return float(v) if v is not None else None
 
 
+def host_cpu_model():
+    """CPU model name of the host (Linux), or the platform's processor string."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(h, nocc, iters=2):
     """Oracle FP64 purification (numpy) on the host, `iters` iterations."""
     from oracle import canonical
@@ -96,7 +109,7 @@ def cpu_baseline(h, nocc, iters=2):
     n = h.shape[0]
     flops = r["iters"] * 2 * 2.0 * n ** 3
     return dict(value=flops / dt / 1e12, unit="TFLOP/s (FP64-equivalent)", cores=int(threads),
-                kind="oracle",
+                kind="oracle", host=host_cpu_model(),
                 sample=f"{r['iters']} canonical-purification iterations (initial guess + "
                        f"{2 * r['iters']} FP64 numpy products) of the n={n} workload, "
                        f"{dt:.1f} s")
