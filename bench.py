@@ -591,8 +591,8 @@ def main():
                                                 if peak and dom.get("clock_ghz") else None),
                      "traffic": (profiled_traffic(a.kind, a.slices) if a.workload == "tb_8192"
                                  else None),
-                     "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE/WRITE_SIZE, "
-                                     "copy-calibrated)",
+                     "traffic_unit": "bytes per product, summed over its launches (HBM, "
+                                     "rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
                      "kernels": kernels},
         "native_fp64": native,
         "trs4": trs4,
