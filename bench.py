@@ -64,9 +64,9 @@ def kernel_code_digest(path):
 
 
 def profiled_traffic(kind, slices, which="update"):
-    """HBM bytes per launch of the slice GEMM from the committed rocprofv3
-    counter summary, or None when that summary was taken on another version
-    of the kernel code (or for another configuration)."""
+    """HBM bytes per product of the slice GEMM (summed over its launches) from
+    the committed rocprofv3 counter summary, or None when that summary was
+    taken on another version of the kernel code (or for another configuration)."""
     path = os.path.join(ROOT, "profiles", f"k_ozgemm_{kind}_s{slices}_tb8192_traffic.md")
     src = os.path.join(ROOT, "paper_2407_13299_amd", "csrc", "ozgemm.hip")
     if not os.path.exists(path):
