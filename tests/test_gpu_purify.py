@@ -185,11 +185,13 @@ def test_fully_degenerate_spectrum():
     assert info["idem"] > 1.0
 
 
+@pytest.mark.parametrize("dims", [(4, 5, 6), (8, 8, 8)])
 @pytest.mark.parametrize("method", ["canonical", "trs4"])
-def test_graph_replays_equal_eager_launches(method, monkeypatch):
+def test_graph_replays_equal_eager_launches(method, dims, monkeypatch):
     """Iterations run from a captured hipGraph, replayed many times per call,
-    give the same iterates bit for bit as eager launches."""
-    h = tight_binding_hamiltonian(4, 5, 6, seed=13)
+    give the same iterates bit for bit as eager launches (n = 480, and
+    n = 2048, whose slice GEMMs run with a split tail)."""
+    h = tight_binding_hamiltonian(*dims, seed=13)
     nocc = h.shape[0] // 4
     p_graph, e_graph, i_graph = gpu_purify(h, nocc, tol=1e-10, slices=7, method=method)
     monkeypatch.setenv("DMP_NO_GRAPH", "1")
