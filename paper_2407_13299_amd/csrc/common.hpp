@@ -166,6 +166,17 @@ struct PurDesc {
     int pad_;
 };
 
+// Coefficient step run by extra blocks of a split launch (count > 0): block
+// b < count computes the update weights of matrix b from the square's trace
+// partials (method: DMP_CANONICAL or DMP_TRS4), the split's units follow.  The split of X2 reads only
+// the done flags of the states these blocks write.
+struct CoefArgs {
+    const PurDesc* pd;
+    DevState* st;
+    int count;
+    int method;
+};
+
 // Epilogue modes of the slice GEMM.
 enum EpiMode : int {
     EPI_STORE = 0,     // C = A B (general, full tiles)

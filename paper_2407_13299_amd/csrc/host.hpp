@@ -56,8 +56,11 @@ int launch_split_digits(const SplitDesc& d, int S, dmp_kind kind, const DevState
                         hipStream_t stream);
 int launch_split_grouped_rowmax(const SplitDesc* descs_dev, int count, int units,
                                 const DevState* st, hipStream_t stream);
+// coef.count > 0: the same launch also runs the coefficient step of the
+// matrices (extra blocks ahead of the split's units)
 int launch_split_grouped_digits(const SplitDesc* descs_dev, int count, int units, int S,
-                                dmp_kind kind, const DevState* st, hipStream_t stream);
+                                dmp_kind kind, const DevState* st, hipStream_t stream,
+                                const CoefArgs& coef = CoefArgs{});
 int split_units_rowmax(int R);
 int split_units_digits(int R, int KC);
 

@@ -12,6 +12,7 @@
 //
 // Output layout: see common.hpp (fragment blocks of 1 KiB, S planes of one
 // (32-row block, chunk) adjacent).
+#include "coef.hpp"
 #include "common.hpp"
 
 #include <hip/hip_fp16.h>
@@ -187,20 +188,30 @@ __device__ inline int exponent_of(uint64_t bits) {
 // rows, which are adjacent in memory.
 // HALVES (Markidis kind, S = 2, FP16): instead of digits, the high and low
 // FP16 parts of x = a 2^-e (|x| < 1): X0 = FP16[x], X1 = FP16[x - X0].
+// coef.count > 0: the first coef.count blocks of the grid run the coefficient
+// step of the matrices instead (CoefArgs), beside the split's units.
 template <int S, bool FP16, bool HALVES = false>
 __global__ __launch_bounds__(256) void k_digits(const SplitDesc* descs, int count,
-                                                SplitDesc one, const DevState* st) {
+                                                SplitDesc one, const DevState* st, CoefArgs coef) {
     constexpr int CK = FP16 ? 16 : 32;
     constexpr int NE = CK / 2;
     constexpr int W = 4 * CK;
     constexpr int LDW = W + 2;   // row stride in doubles: rows start 4 banks apart
     constexpr int PER = kFragRows * W / 256;
     __shared__ double panel[kFragRows * LDW];
+    if (int(blockIdx.x) < coef.count) {
+        const int m = blockIdx.x;
+        if (coef.method == DMP_TRS4)
+            coef_trs4(coef.pd[m], coef.st[m], panel);
+        else
+            coef_canonical(coef.pd[m], coef.st[m], panel);
+        return;
+    }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int local;
     // a copy: held in scalar registers, so that the LDS stores below cannot
     // alias it and force its fields to be reloaded
-    const SplitDesc d = pick<false>(descs, count, one, blockIdx.x, &local);
+    const SplitDesc d = pick<false>(descs, count, one, int(blockIdx.x) - coef.count, &local);
     if (skipped(d, st)) return;
     const int rb_count = int(round_up(d.R, kPad)) / kFragRows;
     const int kq_count = (d.KC + 3) / 4;
@@ -330,15 +341,16 @@ __global__ __launch_bounds__(256) void k_digits(const SplitDesc* descs, int coun
 
 template <int S>
 static void launch_digits_s(bool fp16, const SplitDesc* descs, int count, const SplitDesc& one,
-                            const DevState* st, int units, hipStream_t stream) {
+                            const DevState* st, int units, const CoefArgs& coef,
+                            hipStream_t stream) {
     if (fp16)
-        k_digits<S, true><<<units, 256, 0, stream>>>(descs, count, one, st);
+        k_digits<S, true><<<units + coef.count, 256, 0, stream>>>(descs, count, one, st, coef);
     else
-        k_digits<S, false><<<units, 256, 0, stream>>>(descs, count, one, st);
+        k_digits<S, false><<<units + coef.count, 256, 0, stream>>>(descs, count, one, st, coef);
 }
 
 using DigitsFn = void (*)(bool, const SplitDesc*, int, const SplitDesc&, const DevState*, int,
-                          hipStream_t);
+                          const CoefArgs&, hipStream_t);
 static const DigitsFn kDigits[kMaxSlices + 1] = {
     nullptr,           launch_digits_s<1>,  launch_digits_s<2>,  launch_digits_s<3>,
     launch_digits_s<4>, launch_digits_s<5>,  launch_digits_s<6>,  launch_digits_s<7>,
@@ -363,9 +375,11 @@ int launch_split(const SplitDesc& d, int S, dmp_kind kind, const DevState* st,
         if (d.K > 0) k_colmax<<<split_units_colmax(d.R, d.K), 256, 0, stream>>>(nullptr, 0, d, st);
     }
     if (kind == DMP_MARKIDIS_FP16)
-        k_digits<2, true, true><<<split_units_digits(d.R, d.KC), 256, 0, stream>>>(nullptr, 0, d, st);
+        k_digits<2, true, true><<<split_units_digits(d.R, d.KC), 256, 0, stream>>>(nullptr, 0, d, st,
+                                                                                  CoefArgs{});
     else
-        kDigits[S](kind == DMP_OZ_FP16, nullptr, 0, d, st, split_units_digits(d.R, d.KC), stream);
+        kDigits[S](kind == DMP_OZ_FP16, nullptr, 0, d, st, split_units_digits(d.R, d.KC),
+                   CoefArgs{}, stream);
     DMP_CHECK_HIP(hipGetLastError());
     return DMP_OK;
 }
@@ -376,9 +390,11 @@ int launch_split_digits(const SplitDesc& d, int S, dmp_kind kind, const DevState
                         hipStream_t stream) {
     if (round_up(d.R, kPad) == 0) return DMP_OK;
     if (kind == DMP_MARKIDIS_FP16)
-        k_digits<2, true, true><<<split_units_digits(d.R, d.KC), 256, 0, stream>>>(nullptr, 0, d, st);
+        k_digits<2, true, true><<<split_units_digits(d.R, d.KC), 256, 0, stream>>>(nullptr, 0, d, st,
+                                                                                  CoefArgs{});
     else
-        kDigits[S](kind == DMP_OZ_FP16, nullptr, 0, d, st, split_units_digits(d.R, d.KC), stream);
+        kDigits[S](kind == DMP_OZ_FP16, nullptr, 0, d, st, split_units_digits(d.R, d.KC),
+                   CoefArgs{}, stream);
     DMP_CHECK_HIP(hipGetLastError());
     return DMP_OK;
 }
@@ -393,11 +409,14 @@ int launch_split_grouped_rowmax(const SplitDesc* descs_dev, int count, int units
 }
 
 int launch_split_grouped_digits(const SplitDesc* descs_dev, int count, int units, int S,
-                                dmp_kind kind, const DevState* st, hipStream_t stream) {
-    if (units > 0 && kind == DMP_MARKIDIS_FP16)
-        k_digits<2, true, true><<<units, 256, 0, stream>>>(descs_dev, count, SplitDesc{}, st);
-    else if (units > 0)
-        kDigits[S](kind == DMP_OZ_FP16, descs_dev, count, SplitDesc{}, st, units, stream);
+                                dmp_kind kind, const DevState* st, hipStream_t stream,
+                                const CoefArgs& coef) {
+    if (units + coef.count <= 0) return DMP_OK;
+    if (kind == DMP_MARKIDIS_FP16)
+        k_digits<2, true, true><<<units + coef.count, 256, 0, stream>>>(descs_dev, count,
+                                                                       SplitDesc{}, st, coef);
+    else
+        kDigits[S](kind == DMP_OZ_FP16, descs_dev, count, SplitDesc{}, st, units, coef, stream);
     DMP_CHECK_HIP(hipGetLastError());
     return DMP_OK;
 }
