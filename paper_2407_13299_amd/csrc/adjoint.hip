@@ -59,6 +59,9 @@ struct OzCtx {
     int nt_up = 0;                      // products and the symmetric store)
     const Tile* tiles_full = nullptr;
     int nt_full = 0;
+    int* fix = nullptr;                 // part buffer of the split tail of
+    int fix_pieces = 0;                 // the purification products
+    TailSplit tail{0, 1};
 };
 
 void carve_ctx(Carver& c, OzCtx& x, int n, int S, dmp_kind kind) {
@@ -83,6 +86,9 @@ void carve_ctx(Carver& c, OzCtx& x, int n, int S, dmp_kind kind) {
     x.scal = c.take<double>(8);
     x.pd = c.take<PurDesc>(1);
     x.st = c.take<DevState>(1);
+    x.fix_pieces = (kind == DMP_OZ_INT8 || kind == DMP_OZ_FP16)
+                       ? tail_split_capacity(upper_tile_count(n, 32 * x.rb), x.KC) : 0;
+    x.fix = x.fix_pieces > 0 ? c.take<int>(size_t(x.fix_pieces) * piece_ints(S, x.rb)) : nullptr;
 }
 
 int bind_ctx(OzCtx& x, const double* H, int nocc, double* P0, hipStream_t s) {
@@ -93,6 +99,12 @@ int bind_ctx(OzCtx& x, const double* H, int nocc, double* P0, hipStream_t s) {
     DMP_CHECK(cached_tiles(tm, tn, false, &x.tiles_full, TM));
     x.nt_up = upper_tile_count(x.n, TM);
     x.nt_full = tm * tn;
+    x.tail = TailSplit{x.nt_up, 1};
+    if (x.fix != nullptr && tail_split_enabled()) {
+        int slots = 0;
+        DMP_CHECK(gemm_slots(x.S, x.kind, x.rb, &slots));
+        x.tail = plan_tail_split(x.nt_up, slots, x.KC, x.fix_pieces);
+    }
     PurDesc d{};
     d.H = H;
     d.Pb[0] = P0;
@@ -156,6 +168,11 @@ int forward_iteration(const OzCtx& x, const double* P_in, double* X2_out, double
     p.partials = x.partials;
     p.states = x.st;
     p.mode = EPI_SQUARE;
+    if (x.tail.nsplit > 1) {   // the split tail of the purification products
+        p.fix = x.fix;
+        p.nfull = x.tail.nfull;
+        p.nsplit = x.tail.nsplit;
+    }
     DMP_CHECK(launch_ozgemm(x.S, x.kind, p, x.nt_up, s, x.rb));
     DMP_CHECK(launch_finalize_coef(x.pd, x.st, 1, s));
     DMP_CHECK(launch_split(split_of(x, X2_out, false, x.mb, x.eb, x.pb, 0), x.S, x.kind, x.st, s));

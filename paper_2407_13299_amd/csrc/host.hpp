@@ -91,6 +91,8 @@ struct TailSplit {
 // kMaxSplit, at least kMinSplitChunks of the ``min_kc`` chunks each, at most
 // ``max_pieces`` parts in all).
 TailSplit plan_tail_split(int ntiles, int slots, int min_kc, int max_pieces);
+// DMP_TAIL_SPLIT = 0 keeps every tile whole (for measurements).
+bool tail_split_enabled();
 // Parts of a tail split a group of ``ntiles`` tiles may need (the size of its
 // part buffer in pieces, 0 when no split can arise).
 int tail_split_capacity(int ntiles, int min_kc);

@@ -463,6 +463,11 @@ int e0_blocks() { return kE0Blocks; }
 // spills.  DMP_TILE_ROWS = 64 or 128 forces one height where both exist
 // (for measurements).  A function of (kind, S, n) only, so a matrix gets the
 // same tiles, hence bit-identical results, alone, in a batch or in the tape.
+bool tail_split_enabled() {
+    const char* e = std::getenv("DMP_TAIL_SPLIT");
+    return !(e && std::strcmp(e, "0") == 0);
+}
+
 int tile_blocks_for(dmp_kind kind, int S, int n) {
     (void)n;
     if ((kind != DMP_OZ_INT8 && kind != DMP_OZ_FP16) || S > 7) return 4;
@@ -518,12 +523,6 @@ MatLayout carve_matrix(Carver& c, int n, int S, dmp_kind kind) {
     m.rowbad = c.take<int>(n);
     m.e0 = c.take<double>(kE0Blocks);
     return m;
-}
-
-// DMP_TAIL_SPLIT = 0 keeps every tile whole (for measurements).
-bool tail_split_enabled() {
-    const char* e = std::getenv("DMP_TAIL_SPLIT");
-    return !(e && std::strcmp(e, "0") == 0);
 }
 
 // Everything a group of matrices (same S and kind) needs on the device.
