@@ -137,6 +137,11 @@ int dmp_max_slices(dmp_kind kind);
  *   k 2^(e_i + f_j) (S + 3) 2^(2 - 8S) + (S + 2) 2^-53 (|A||B|)_ij of the
  *   exact product, where 2^(e_i - 1) <= max|row i of op(A)| < 2^e_i and f_j
  *   likewise for column j of op(B).  Asynchronous on ``stream``.
+ *   The workspace size depends on the current device as well: when the
+ *   output tiles do not fill whole rounds of its CUs, it includes a buffer
+ *   for the last round's partial sums.  Query on the device that runs the
+ *   product (DMP_TAIL_SPLIT=0 in the environment, at query and at run time,
+ *   keeps every tile whole and the buffer out).
  * ------------------------------------------------------------------- */
 size_t dmp_gemm_workspace_bytes(int m, int n, int k, int slices, dmp_kind kind);
 int dmp_ozaki_gemm(char transA, char transB, int m, int n, int k,

@@ -87,7 +87,7 @@ void carve_ctx(Carver& c, OzCtx& x, int n, int S, dmp_kind kind) {
     x.pd = c.take<PurDesc>(1);
     x.st = c.take<DevState>(1);
     x.fix_pieces = (kind == DMP_OZ_INT8 || kind == DMP_OZ_FP16)
-                       ? tail_split_capacity(upper_tile_count(n, 32 * x.rb), x.KC) : 0;
+                       ? tail_split_capacity(upper_tile_count(n, 32 * x.rb), x.KC, x.rb) : 0;
     x.fix = x.fix_pieces > 0 ? c.take<int>(size_t(x.fix_pieces) * piece_ints(S, x.rb)) : nullptr;
 }
 

@@ -206,8 +206,7 @@ struct GemmParams {
     // nullable (kernel timing): [0] += shader-clock cycles and [1] += 100 MHz
     // real-time ticks of every workgroup, from its start to its end
     unsigned long long* clk;
-    // Reduction split of the last tiles (purification modes; ``fix`` null: no
-    // split).  Blocks [0, nfull) own tiles [0, nfull) whole.  Block nfull + u
+    // Reduction split of the last tiles (``fix`` null: no split).  Blocks [0, nfull) own tiles [0, nfull) whole.  Block nfull + u
     // owns part u % nsplit of tile nfull + u / nsplit: it reduces the chunks
     // [KC part / nsplit, KC (part + 1) / nsplit) and stores its INT32 group
     // sums at piece u of ``fix`` instead of running the epilogue.  The fixup

@@ -15,16 +15,43 @@ struct GemmLayout {
     int* eb;
     uint64_t* ma;
     uint64_t* mb;
+    int* fix;          // part buffer of the split tail (nullable)
+    TailSplit tail;
 };
 
-GemmLayout carve_gemm(Carver& c, int m, int n, int k, int s, dmp_kind kind) {
+// Split tail of the m x n product's 128 x 64 tiles on the current device; the
+// workspace query and the launch take the same plan, so the part buffer is
+// only as large as the launch needs (none when the tiles fill whole rounds).
+TailSplit gemm_tail(int m, int n, int k, int s, dmp_kind kind) {
+    const int tiles = m > 0 && n > 0 ? tile_rows(m) * tile_cols(n) : 0;
+    TailSplit t{tiles, 1};
+    if ((kind != DMP_OZ_INT8 && kind != DMP_OZ_FP16) || k <= 0 || tiles == 0 ||
+        !tail_split_enabled())
+        return t;
+    const int kc = int(chunks_of(k, kind));
+    const int cap = tail_split_capacity(tiles, kc, 4);
+    int slots = 0;
+    if (cap <= 0 || gemm_slots(s, kind, 4, &slots) != DMP_OK) {
+        clear_error();
+        return t;
+    }
+    return plan_tail_split(tiles, slots, kc, cap);
+}
+
+// ``split``: plan a split tail (single products; the grouped launch keeps
+// its tiles whole)
+GemmLayout carve_gemm(Carver& c, int m, int n, int k, int s, dmp_kind kind, bool split = false) {
     GemmLayout g;
+    g.tail = split ? gemm_tail(m, n, k, s, kind) : TailSplit{0, 1};
     g.pa = c.take<uint8_t>(plane_bytes(m, k, s, kind));
     g.pb = c.take<uint8_t>(plane_bytes(n, k, s, kind));
     g.ea = c.take<int>(round_up(m, kPad));
     g.eb = c.take<int>(round_up(n, kPad));
     g.ma = c.take<uint64_t>(round_up(m, kPad));
     g.mb = c.take<uint64_t>(round_up(n, kPad));
+    const int tiles = m > 0 && n > 0 ? tile_rows(m) * tile_cols(n) : 0;
+    const size_t parts = g.tail.nsplit > 1 ? size_t(tiles - g.tail.nfull) * g.tail.nsplit : 0;
+    g.fix = parts > 0 ? c.take<int>(parts * piece_ints(s, 4)) : nullptr;
     return g;
 }
 
@@ -49,7 +76,7 @@ size_t dmp_gemm_workspace_bytes(int m, int n, int k, int slices, dmp_kind kind) 
     if (m < 0 || n < 0 || k < 0 || slices < 1 || slices > kMaxSlices) return 0;
     if (kind == DMP_MARKIDIS_FP16 && slices > kMaxTerms) return 0;
     Carver c(nullptr);
-    carve_gemm(c, m, n, k, slices, kind);
+    carve_gemm(c, m, n, k, slices, kind, true);
     return c.used();
 }
 
@@ -100,7 +127,7 @@ int dmp_ozaki_gemm(char transA, char transB, int m, int n, int k, const double* 
         return DMP_ENOMEM;
     }
     Carver c(ws);
-    GemmLayout g = carve_gemm(c, m, n, k, slices, kind);
+    GemmLayout g = carve_gemm(c, m, n, k, slices, kind, true);
     const int KC = int(chunks_of(k, kind));
     const int64_t rb_stride = int64_t(KC) * planes_of(slices, kind) * kFragBytes;
 
@@ -145,6 +172,11 @@ int dmp_ozaki_gemm(char transA, char transB, int m, int n, int k, const double* 
     p.one.ldc = ldc;
     p.one.state_index = -1;
     p.mode = EPI_STORE;
+    if (g.fix != nullptr) {
+        p.fix = g.fix;
+        p.nfull = g.tail.nfull;
+        p.nsplit = g.tail.nsplit;
+    }
     return launch_ozgemm(slices, kind, p, tm * tn, s);
 }
 

@@ -176,10 +176,12 @@ TailSplit plan_tail_split(int ntiles, int slots, int min_kc, int max_pieces) {
     return t;
 }
 
-int tail_split_capacity(int ntiles, int min_kc) {
+int tail_split_capacity(int ntiles, int min_kc, int rb) {
     const int parts = split_parts_max(min_kc);
     if (parts < 2 || ntiles <= 0) return 0;
-    return int(std::min<int64_t>(kMaxPieces, int64_t(ntiles) * parts));
+    // 128-row tiles: one workgroup per CU, so half the parts run at once
+    const int cap = rb == 4 ? kMaxPieces / 2 : kMaxPieces;
+    return int(std::min<int64_t>(cap, int64_t(ntiles) * parts));
 }
 
 int64_t chunks_of(int k, dmp_kind kind) { return round_up(k, kKPad) / chunk_k(kind); }

@@ -93,9 +93,9 @@ struct TailSplit {
 TailSplit plan_tail_split(int ntiles, int slots, int min_kc, int max_pieces);
 // DMP_TAIL_SPLIT = 0 keeps every tile whole (for measurements).
 bool tail_split_enabled();
-// Parts of a tail split a group of ``ntiles`` tiles may need (the size of its
-// part buffer in pieces, 0 when no split can arise).
-int tail_split_capacity(int ntiles, int min_kc);
+// Parts of a tail split a group of ``ntiles`` tiles of height 32 rb may need
+// (the size of its part buffer in pieces, 0 when no split can arise).
+int tail_split_capacity(int ntiles, int min_kc, int rb);
 
 int native_dsyrk_upper(hipStream_t stream, int n, const double* A, double* C);
 int native_dsyrkx_upper(hipStream_t stream, int n, const double* A, const double* B, double* C);

@@ -98,7 +98,7 @@ __global__ __launch_bounds__(128 * RB, RB == 4 ? 1 : 2) void k_ozgemm(GemmParams
     __shared__ __align__(16) uint8_t lds[2][STAGE];
     __shared__ double red[WAVES][kPartials];
 
-    static_assert(PHASE == kWhole || (PUR && TERMS == 0), "tail split: purification modes, Ozaki kinds");
+    static_assert(PHASE == kWhole || TERMS == 0, "tail split: Ozaki kinds");
     // XCD-aware block order: the hardware hands consecutive blocks to the 8
     // XCDs in turn; give every XCD one contiguous slice of the tile list.
     const int b = blockIdx.x;
@@ -501,20 +501,22 @@ static bool purification_mode(int mode) {
     return mode == EPI_SQUARE || mode == EPI_UPDATE || mode == EPI_SQUARE_TRS4;
 }
 
+// The parts of a split tail run no epilogue, so one instantiation (the
+// purification one) serves every mode.
 template <int S, int PHASE>
 static void launch_s(bool fp16, const GemmParams& p, int ntiles, int rb, hipStream_t stream) {
-    const bool pur = purification_mode(p.mode);
+    const bool pur = PHASE == kPiece || purification_mode(p.mode);
     if constexpr (S <= 7) {   // the 64-row variant exists up to S = 7
         if (rb == 2) {
             if (fp16 && pur)
                 k_ozgemm<S, true, 0, true, 2, PHASE><<<ntiles, 256, 0, stream>>>(p);
             else if (pur)
                 k_ozgemm<S, false, 0, true, 2, PHASE><<<ntiles, 256, 0, stream>>>(p);
-            else if constexpr (PHASE == kWhole) {
+            else if constexpr (PHASE != kPiece) {
                 if (fp16)
-                    k_ozgemm<S, true, 0, false, 2><<<ntiles, 256, 0, stream>>>(p);
+                    k_ozgemm<S, true, 0, false, 2, PHASE><<<ntiles, 256, 0, stream>>>(p);
                 else
-                    k_ozgemm<S, false, 0, false, 2><<<ntiles, 256, 0, stream>>>(p);
+                    k_ozgemm<S, false, 0, false, 2, PHASE><<<ntiles, 256, 0, stream>>>(p);
             }
             return;
         }
@@ -523,11 +525,11 @@ static void launch_s(bool fp16, const GemmParams& p, int ntiles, int rb, hipStre
         k_ozgemm<S, true, 0, true, 4, PHASE><<<ntiles, kGemmThreads, 0, stream>>>(p);
     } else if (pur) {
         k_ozgemm<S, false, 0, true, 4, PHASE><<<ntiles, kGemmThreads, 0, stream>>>(p);
-    } else if constexpr (PHASE == kWhole) {
+    } else if constexpr (PHASE != kPiece) {
         if (fp16)
-            k_ozgemm<S, true, 0, false><<<ntiles, kGemmThreads, 0, stream>>>(p);
+            k_ozgemm<S, true, 0, false, 4, PHASE><<<ntiles, kGemmThreads, 0, stream>>>(p);
         else
-            k_ozgemm<S, false, 0, false><<<ntiles, kGemmThreads, 0, stream>>>(p);
+            k_ozgemm<S, false, 0, false, 4, PHASE><<<ntiles, kGemmThreads, 0, stream>>>(p);
     }
 }
 
@@ -583,7 +585,7 @@ int launch_ozgemm(int S, dmp_kind kind, const GemmParams& p, int ntiles, hipStre
     }
     if (p.fix != nullptr) {
         const int tail = ntiles - p.nfull;
-        if (kind == DMP_MARKIDIS_FP16 || !purification_mode(p.mode) || p.nfull < 0 || tail < 1 ||
+        if (kind == DMP_MARKIDIS_FP16 || p.nfull < 0 || tail < 1 ||
             p.nsplit < 2 || int64_t(tail) * p.nsplit > kMaxPieces) {
             set_error("invalid tail split (nfull %d of %d tiles, %d parts)", p.nfull, ntiles, p.nsplit);
             return DMP_EINVAL;

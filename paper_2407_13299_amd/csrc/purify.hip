@@ -573,7 +573,7 @@ size_t carve_group(Carver& c, GroupPlan& g, const int* n) {
     // part buffer of the tail split (Ozaki kinds), sized for the largest
     // matrix, so that a batch needs no less workspace than any of its members
     g.fix_pieces = (g.kind == DMP_OZ_INT8 || g.kind == DMP_OZ_FP16)
-                       ? tail_split_capacity(int(parts), g.max_kc) : 0;
+                       ? tail_split_capacity(int(parts), g.max_kc, g.rb) : 0;
     g.fix = g.fix_pieces > 0 ? c.take<int>(size_t(g.fix_pieces) * piece_ints(g.S, g.rb)) : nullptr;
     // the refinement step reuses the partials of one matrix's tile pairs
     parts = std::max<size_t>(parts, size_t(g.max_pairs));

@@ -45,6 +45,24 @@ def test_bitwise_many_slices(kind, s):
     assert np.array_equal(run(a, b, s, kind), ozaki.ozaki_gemm(a, b, s))
 
 
+@pytest.mark.parametrize("kind", ["int8", "fp16"])
+def test_split_tail_general_gemm(kind, monkeypatch):
+    """A 2200 x 2200 product has 630 tiles of 128 x 64, more than the chip
+    holds at once; its last round runs in parts along the reduction.  The
+    result equals whole tiles (DMP_TAIL_SPLIT=0) bit for bit, and the oracle
+    on sampled rows, two of them in the split tiles (rows >= 2048)."""
+    rng = np.random.default_rng(21)
+    a = rng.standard_normal((2200, 1500)) * np.exp(rng.uniform(-4, 4, (2200, 1)))
+    b = rng.standard_normal((1500, 2200))
+    monkeypatch.setenv("DMP_TAIL_SPLIT", "1")
+    c1 = run(a, b, 7, kind)
+    monkeypatch.setenv("DMP_TAIL_SPLIT", "0")
+    c0 = run(a, b, 7, kind)
+    assert np.array_equal(c1, c0)
+    rows = [0, 700, 2100, 2199]
+    assert np.array_equal(c1[rows], ozaki.ozaki_gemm(a[rows], b, 7))
+
+
 @pytest.mark.parametrize("ta,tb", [(False, True), (True, False), (True, True)])
 def test_transposes_bitwise(ta, tb):
     rng = np.random.default_rng(7)
