@@ -102,7 +102,7 @@ int bind_ctx(OzCtx& x, const double* H, int nocc, double* P0, hipStream_t s) {
     x.tail = TailSplit{x.nt_up, 1};
     if (x.fix != nullptr && tail_split_enabled()) {
         int slots = 0;
-        DMP_CHECK(gemm_slots(x.S, x.kind, x.rb, &slots));
+        DMP_CHECK(resident_slots(x.S, x.kind, x.rb, &slots));
         x.tail = plan_tail_split(x.nt_up, slots, x.KC, x.fix_pieces);
     }
     PurDesc d{};

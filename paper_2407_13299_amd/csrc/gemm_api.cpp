@@ -31,7 +31,7 @@ TailSplit gemm_tail(int m, int n, int k, int s, dmp_kind kind) {
     const int kc = int(chunks_of(k, kind));
     const int cap = tail_split_capacity(tiles, kc, 4);
     int slots = 0;
-    if (cap <= 0 || gemm_slots(s, kind, 4, &slots) != DMP_OK) {
+    if (cap <= 0 || resident_slots(s, kind, 4, &slots) != DMP_OK) {
         clear_error();
         return t;
     }

@@ -161,6 +161,27 @@ int check_kind_slices(dmp_kind kind, int slices) {
     return DMP_OK;
 }
 
+int resident_slots(int S, dmp_kind kind, int rb, int* slots) {
+    int dev = 0;
+    DMP_CHECK_HIP(hipGetDevice(&dev));
+    // a property of the device and the kernel: queried once, then cached
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, int>, int> cache;
+    const auto key = std::make_tuple(dev, S, int(kind), rb);
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            *slots = it->second;
+            return DMP_OK;
+        }
+    }
+    DMP_CHECK(gemm_slots(S, kind, rb, slots));
+    std::lock_guard<std::mutex> lock(mu);
+    cache[key] = *slots;
+    return DMP_OK;
+}
+
 static int split_parts_max(int min_kc) { return std::min(kMaxSplit, min_kc / kMinSplitChunks); }
 
 TailSplit plan_tail_split(int ntiles, int slots, int min_kc, int max_pieces) {

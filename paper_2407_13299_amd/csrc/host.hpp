@@ -78,6 +78,8 @@ int launch_ozgemm(int S, dmp_kind kind, const GemmParams& p, int ntiles, hipStre
 // Workgroups of the purification-mode slice GEMM (kind, S, rb) resident on
 // the current device at once (CUs x workgroups per CU).
 int gemm_slots(int S, dmp_kind kind, int rb, int* slots);
+// gemm_slots cached per device (the query costs microseconds per call)
+int resident_slots(int S, dmp_kind kind, int rb, int* slots);
 
 // Tail split of ``ntiles`` tiles of equal cost: tiles [0, nfull) whole, the
 // rest in nsplit parts each (nsplit == 1: no split).

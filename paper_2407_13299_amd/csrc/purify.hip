@@ -726,7 +726,7 @@ int upload_group(GroupPlan& g, const double* const* H, double* const* P, const i
     g.tail = TailSplit{g.ntiles, 1};
     if (g.fix != nullptr && tail_split_enabled()) {
         int slots = 0;
-        DMP_CHECK(gemm_slots(g.S, g.kind, g.rb, &slots));
+        DMP_CHECK(resident_slots(g.S, g.kind, g.rb, &slots));
         g.tail = plan_tail_split(g.ntiles, slots, g.min_kc, g.fix_pieces);
     }
     g.units_rowmax = urow;
