@@ -7,13 +7,13 @@ after the power-of-two row (column) scaling of the Ozaki scheme that the
 paper applied to the Markidis method as well (Sec. 4.5): rows of A are
 scaled by 2^-e_i and columns of B by 2^-f_j with the frexp exponents of their
 largest entries, so every scaled value lies in (-1, 1).  The product keeps
-1 to 4 terms, in the order Table 3 defines them:
+1 to 4 terms, in the order Table 2 defines them:
     1 term   A0 B0
     2 terms  + A0 B1
     3 terms  + A1 B0
     4 terms  + A1 B1
 and the method accumulates them in FP32 on FP16 tensor units.  Reading: the
-fourth term of Table 3's caption repeats A0 B0, which the four-term product
+fourth term of Table 2's caption repeats A0 B0, which the four-term product
 written in Sec. 4.5 shows to be A1 B1.
 
 ``markidis_gemm`` forms the kept terms in FP64 (each FP16 x FP16 product is

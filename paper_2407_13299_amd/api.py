@@ -251,14 +251,22 @@ class PurifyTape:
 
     def backward(self, Pbar, stream=None):
         lib = _lib.load()
-        _check_out(Pbar, (self.n, self.n), self.P, "Pbar")
-        Pbar = 0.5 * (Pbar + Pbar.T)
+        if not isinstance(Pbar, torch.Tensor) or Pbar.dim() != 2:
+            raise TypeError("Pbar must be a 2-D float64 CUDA (HIP) tensor")
+        # dmp_purify_bwd symmetrises Pbar itself (the adjoint of a symmetric
+        # P); only the layout is fixed here
         Pbar = Pbar.contiguous()
+        _check_out(Pbar, (self.n, self.n), self.P, "Pbar")
         Hbar = torch.empty_like(Pbar)
         ws = _workspace(lib.dmp_purify_bwd_workspace_bytes(self._tape), self.device)
+        if stream is not None:
+            # Pbar, Hbar and the workspace were produced or allocated on the
+            # current stream: the library's stream starts after them
+            stream.wait_stream(torch.cuda.current_stream())
         st = lib.dmp_purify_bwd(self._tape, _ptr(Pbar), _ptr(Hbar), _ptr(ws), ws.numel(),
                                 _stream(stream))
         _lib.check(st, "dmp_purify_bwd")
+        _keep_for(ws, stream)
         return Hbar
 
     def __del__(self):

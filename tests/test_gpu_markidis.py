@@ -1,5 +1,5 @@
 """GPU parity of the Markidis-scheme product (Sec. 4.5) and its use in
-purification, set beside the Ozaki scheme (the comparison of Table 3)."""
+purification, set beside the Ozaki scheme (the comparison of Table 2, Sec. 4.5)."""
 import numpy as np
 import pytest
 
@@ -91,7 +91,7 @@ def test_markidis_purification_accuracy_class():
 
 def test_markidis_vs_ozaki_table():
     """Errors and iterations against the number of terms on the n = 2048
-    tight-binding workload (the layout of Table 3: RMSD, commutator, energy,
+    tight-binding workload (the layout of Table 2: RMSD, commutator, energy,
     energy after one FP64 McWeeny step, iterations), with Ozaki S = 5 and 7
     and FP64 beside them."""
     w = workload("tb_2048")

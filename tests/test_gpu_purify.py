@@ -42,6 +42,29 @@ def test_small_spectrum(kind, s):
     assert abs(info["trace"] - nocc) < 1e-9
 
 
+# The 4 x 4 matrix of the oracle's hand-computed pins: Gershgorin discs
+# [0.5, 3.5], [-4, 4], [-8, 0], [-0.5, 2.5], so h_min = -8 and h_max = 4;
+# mu = tr H / n = -1/4; lam = 1/17 for nocc = 1 and 1/31 for nocc = 3.
+HAND_H = np.array([[2.0, -1.0, 0.0, 0.5],
+                   [-1.0, 0.0, 3.0, 0.0],
+                   [0.0, 3.0, -4.0, 1.0],
+                   [0.5, 0.0, 1.0, 1.0]])
+
+
+@pytest.mark.parametrize("kind", ["int8", "native"])
+@pytest.mark.parametrize("nocc,lam", [(1, 1.0 / 17.0), (3, 1.0 / 31.0)])
+def test_bounds_and_scalars_hand_computed(kind, nocc, lam):
+    """The device's Gershgorin bounds, mean and scaling against the values
+    worked out by hand (not through the oracle); the run itself converges
+    to the projector."""
+    p, e, info = gpu_purify(HAND_H, nocc, tol=1e-12, slices=7, kind=kind)
+    assert info["h_min"] == -8.0 and info["h_max"] == 4.0
+    assert info["mu"] == -0.25
+    assert info["lambda"] == pytest.approx(lam, rel=1e-15)
+    p_ref, e_ref, _, _ = projector.eigh_projector(HAND_H, nocc)
+    assert np.max(np.abs(p - p_ref)) < TOL_P and abs(e - e_ref) < TOL_E
+
+
 @pytest.mark.parametrize("kind", ["int8", "fp16"])
 def test_tight_binding_2048(kind):
     w = workload("tb_2048")

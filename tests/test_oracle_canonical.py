@@ -139,3 +139,48 @@ def test_gershgorin_encloses_spectrum():
     lo, hi = canonical.gershgorin(h)
     ev = np.linalg.eigvalsh(h)
     assert lo <= ev[0] and ev[-1] <= hi
+
+
+# A 4 x 4 symmetric H whose Gershgorin discs are worked out by hand (Sec. 2.3:
+# lambda maps the spectrum into [0, 1]; the bounds come from the discs
+# centre H_ii, radius sum_{j != i} |H_ij|):
+#   row 0: centre  2, radius 1 + 0 + 0.5 = 1.5 -> [ 0.5, 3.5]
+#   row 1: centre  0, radius 1 + 3 + 0   = 4   -> [-4,   4  ]
+#   row 2: centre -4, radius 0 + 3 + 1   = 4   -> [-8,   0  ]
+#   row 3: centre  1, radius 0.5 + 0 + 1 = 1.5 -> [-0.5, 2.5]
+# so h_min = -8 (row 2) and h_max = 4 (row 1); tr H = -1, mu = -1/4.
+HAND_H = np.array([[2.0, -1.0, 0.0, 0.5],
+                   [-1.0, 0.0, 3.0, 0.0],
+                   [0.0, 3.0, -4.0, 1.0],
+                   [0.5, 0.0, 1.0, 1.0]])
+
+
+def test_gershgorin_hand_computed_bounds():
+    """Fails if the radius also counts |H_ii| (h_max would be 5.5), if the
+    centre's sign is flipped (h_max 8) or if min and max are exchanged."""
+    lo, hi = canonical.gershgorin(HAND_H)
+    assert lo == -8.0 and hi == 4.0
+
+
+def test_initial_scalars_hand_computed():
+    """theta = nocc / n; lam = min(theta / (h_max - mu), (1 - theta) / (mu - h_min)).
+    nocc = 1: 0.25 / 4.25 = 1/17 against 0.75 / 7.75 = 3/31, the first is smaller.
+    nocc = 3: 0.75 / 4.25 = 3/17 against 0.25 / 7.75 = 1/31, the second is."""
+    theta, mu, lam, lo, hi, which = canonical.initial_scalars(HAND_H, 1)
+    assert (theta, mu, lo, hi, which) == (0.25, -0.25, -8.0, 4.0, 0)
+    assert lam == pytest.approx(1.0 / 17.0, rel=1e-15)
+    theta, mu, lam, lo, hi, which = canonical.initial_scalars(HAND_H, 3)
+    assert (theta, mu, which) == (0.75, -0.25, 1)
+    assert lam == pytest.approx(1.0 / 31.0, rel=1e-15)
+
+
+def test_initial_guess_hand_computed():
+    """P0 = lam (mu I - H) + theta I with lam = 1/17, mu = -1/4, theta = 1/4:
+    P0_00 = (-1/4 - 2)/17 + 1/4 = 2/17, P0_01 = 1/17, P0_22 = (-1/4 + 4)/17 + 1/4
+    = 8/17, P0_23 = -1/17; tr P0 = nocc."""
+    p0 = canonical.initial_guess(HAND_H, 1)
+    want = {(0, 0): 2.0 / 17, (0, 1): 1.0 / 17, (2, 2): 8.0 / 17, (2, 3): -1.0 / 17,
+            (1, 3): 0.0}
+    for (i, j), v in want.items():
+        assert p0[i, j] == pytest.approx(v, rel=1e-14, abs=1e-16)
+    assert np.trace(p0) == pytest.approx(1.0, rel=1e-14)
