@@ -40,7 +40,7 @@ def parse():
                     help="slices (default 7; batched_64: 0 = the tuned table)")
     ap.add_argument("--kind", default="int8", choices=["int8", "fp16"])
     ap.add_argument("--workload", default="tb_8192",
-                    choices=["tb_8192", "batched_64", "adjoint_2048", "small_spectrum", "slice_sweep",
+                    choices=["tb_8192", "tb_2048", "batched_64", "adjoint_2048", "small_spectrum", "slice_sweep",
                              "gemm_8192", "slices_8192"])
     ap.add_argument("--native-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -437,8 +437,9 @@ def main():
     for _ in range(a.warmup):
         run(a.kind, a.slices, P, ws)
     torch.cuda.synchronize()
-    lib.dmp_timing_enable(1)
-    lib.dmp_timing_reset()
+    # the timed steps run the default path (cached graph replays, no
+    # instrumentation); the per-kernel times come from a separate pass below
+    lib.dmp_timing_enable(0)
     times, iters = [], []
     torch.cuda.synchronize()
     t_all = time.perf_counter()
@@ -452,6 +453,14 @@ def main():
               f"stop={info['stop']}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     total = time.perf_counter() - t_all
+    # one more (untimed) purification with HIP events around every product:
+    # eager launches on the library's stream, the kernel times of the roofline
+    lib.dmp_timing_enable(1)
+    lib.dmp_timing_reset()
+    t0 = time.perf_counter()
+    run(a.kind, a.slices, P, ws)
+    torch.cuda.synchronize()
+    instrumented_ms = (time.perf_counter() - t0) * 1e3
     lib.dmp_timing_enable(0)
     ms_k = [ctypes.c_double(), ctypes.c_double()]
     nl = [ctypes.c_longlong(), ctypes.c_longlong()]
@@ -489,7 +498,7 @@ def main():
     dom = kernels.get("update") or kernels.get("square") or {}
     peak = INT8_PEAK_TOPS if a.kind == "int8" else FP16_PEAK_TFLOPS
     achieved = dom.get("tops", 0.0)
-    gemm_share = (ms_k[0].value + ms_k[1].value) / (total * 1e3) if total > 0 else 0.0
+    gemm_share = (ms_k[0].value + ms_k[1].value) / instrumented_ms if instrumented_ms > 0 else 0.0
 
     native = None
     if not a.no_native:
@@ -578,7 +587,8 @@ def main():
         "config": {"workload": a.workload, "n": n, "nocc": nocc, "tol": tol,
                    "kind": a.kind, "slices": a.slices, "iterations": it,
                    "products": 2 * it, "slice_products_per_product": a.slices * (a.slices + 1) // 2,
-                   "gemm_time_share": gemm_share, **acc},
+                   "gemm_time_share": gemm_share,
+                   "instrumented_ms": instrumented_ms, **acc},
         "roofline": {"bound": "mfma", "kernel": "k_ozgemm (update: X2 P, upper triangle)",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "ops": "int8 multiply-adds counted as 2 ops" if a.kind == "int8" else "fp16",

@@ -19,7 +19,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libdmp.so")
 ARCH = "gfx950"
 
-SOURCES = ["host.cpp", "gemm_api.cpp", "split.hip", "ozgemm.hip", "purify.hip",
+SOURCES = ["plan.cpp", "host.cpp", "gemm_api.cpp", "split.hip", "ozgemm.hip", "purify.hip",
            "batched.cpp", "adjoint.hip"]
 
 

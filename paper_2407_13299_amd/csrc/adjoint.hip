@@ -23,6 +23,7 @@
 // the quantity the finite-difference and perturbation-theory checks compare.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "host.hpp"
@@ -69,7 +70,8 @@ void carve_ctx(Carver& c, OzCtx& x, int n, int S, dmp_kind kind) {
     x.S = S;
     x.kind = kind;
     x.KC = int(chunks_of(n, kind));
-    x.rb = tile_blocks_for(kind, S, n);
+    const TileChoice tc = tile_choice_env(kind, S, n);
+    x.rb = tc.rb;
     x.rb_stride = int64_t(x.KC) * S * kFragBytes;
     x.pa = c.take<uint8_t>(plane_bytes(n, n, S, kind));
     x.pb = c.take<uint8_t>(plane_bytes(n, n, S, kind));
@@ -86,7 +88,7 @@ void carve_ctx(Carver& c, OzCtx& x, int n, int S, dmp_kind kind) {
     x.scal = c.take<double>(8);
     x.pd = c.take<PurDesc>(1);
     x.st = c.take<DevState>(1);
-    x.fix_pieces = (kind == DMP_OZ_INT8 || kind == DMP_OZ_FP16)
+    x.fix_pieces = (kind == DMP_OZ_INT8 || kind == DMP_OZ_FP16) && tc.split_tail
                        ? tail_split_capacity(upper_tile_count(n, 32 * x.rb), x.KC, x.rb) : 0;
     x.fix = x.fix_pieces > 0 ? c.take<int>(size_t(x.fix_pieces) * piece_ints(S, x.rb)) : nullptr;
 }
@@ -485,6 +487,8 @@ int dmp_purify_fwd_tape(const double* H, int n, int nocc, double tol, int slices
     }
     const int stride = ckpt_stride > 0 ? ckpt_stride
                                        : std::max(1, int(std::ceil(std::sqrt(double(max_iter)))));
+    // one purification at a time per process (see purify_mutex)
+    std::lock_guard<std::mutex> serial(purify_mutex());
     dmp_tape* t = new dmp_tape();
     t->n = n;
     t->nocc = nocc;
@@ -646,6 +650,8 @@ int dmp_purify_bwd(const dmp_tape* t, const double* Pbar, double* Hbar, void* ws
         return DMP_ENOMEM;
     }
     const int n = t->n;
+    // one purification at a time per process (see purify_mutex)
+    std::lock_guard<std::mutex> serial(purify_mutex());
     Carver c(ws);
     OzCtx x;
     double* b[5];
@@ -655,6 +661,7 @@ int dmp_purify_bwd(const dmp_tape* t, const double* Pbar, double* Hbar, void* ws
     DMP_CHECK(bind_ctx(x, t->H, t->nocc, segP[0], s));
     double *Y = b[0], *Yn = b[1], *M = b[2], *MP = b[3], *PM = b[4];
     std::vector<int2> hp = tile_pairs32(n);
+    StreamDrain drain{s};   // ``hp`` outlives its copy, also on an error return
     DMP_CHECK_HIP(hipMemcpyAsync(pairs, hp.data(), hp.size() * sizeof(int2), hipMemcpyHostToDevice, s));
     k_sym<<<unsigned(hp.size()), 256, 0, s>>>(Pbar, Y, n, pairs);
     DMP_CHECK_HIP(hipGetLastError());

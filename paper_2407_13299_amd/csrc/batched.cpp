@@ -4,57 +4,17 @@
 #include <vector>
 
 #include "host.hpp"
-#include "tuned_table.h"
 
 using namespace dmp;
 
 extern "C" {
 
 int dmp_autotune_slices(int n, double target, dmp_kind kind) {
-    if (kind == DMP_FP64_NATIVE) return 0;
-    if (kind == DMP_MARKIDIS_FP16) return kMaxTerms;   // no term count reaches FP64 level
-    if (n < 1 || !(target > 0.0)) return kMaxSlices;
-    // error model max|dP| ~ C n^a 2^-(8S - 1), with (C, a) measured per kind
-    const double c = kind == DMP_OZ_FP16 ? kTunedErrC[1] : kTunedErrC[0];
-    const double a = kind == DMP_OZ_FP16 ? kTunedErrA[1] : kTunedErrA[0];
-    for (int s = 1; s <= kMaxSlices; ++s) {
-        const double err = c * std::pow(double(n), a) * std::ldexp(1.0, -(8 * s - 1));
-        if (err <= target && n <= max_k_for_slices(s)) return s;
-    }
-    return kMaxSlices;
+    return autotune_slices_model(n, target, kind);
 }
 
 }  // extern "C"
 
-namespace {
-
-// Slice count per matrix of a batch.  slices > 0: that count for every
-// matrix.  Otherwise the tuned table's count per matrix; matrices that need
-// fewer slices than the batch maximum then run with the maximum (a larger S
-// is always at least as accurate) when they carry under a quarter of the
-// batch's n^3 work, so that the batch runs as one group of launches instead
-// of one group per slice count.
-void batch_slices(int count, const int* n, int slices, dmp_kind kind, std::vector<int>& s) {
-    s.assign(count, 0);
-    if (kind == DMP_FP64_NATIVE) return;
-    int smax = 0;
-    for (int b = 0; b < count; ++b) {
-        s[b] = slices > 0 ? slices : dmp_autotune_slices(n[b], kTunedTarget, kind);
-        smax = std::max(smax, s[b]);
-    }
-    if (slices > 0 || count < 2) return;
-    double low = 0.0, all = 0.0;
-    for (int b = 0; b < count; ++b) {
-        const double w = double(n[b]) * n[b] * n[b];
-        all += w;
-        if (s[b] < smax) low += w;
-    }
-    if (low >= 0.25 * all) return;
-    for (int b = 0; b < count; ++b)
-        if (n[b] <= max_k_for(smax, kind)) s[b] = smax;
-}
-
-}  // namespace
 
 extern "C" {
 

@@ -296,12 +296,16 @@ int dmp_ozaki_gemm_batched(int count, const int* m, const int* n, const int* k,
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return k[x] > k[y]; });
     for (int b : order) append_tiles(tiles, tile_rows(m[b]), tile_cols(n[b]), false, uint32_t(b));
     Tile* t_dev = c.take<Tile>(tiles.size());
-    DMP_CHECK_HIP(hipMemcpyAsync(sd_dev, sa.data(), count * sizeof(SplitDesc), hipMemcpyHostToDevice, s));
-    DMP_CHECK_HIP(hipMemcpyAsync(md_dev, md.data(), count * sizeof(MatDesc), hipMemcpyHostToDevice, s));
-    DMP_CHECK_HIP(hipMemcpyAsync(t_dev, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, s));
-    // the host vectors must outlive the asynchronous copies; the launches
-    // below stay asynchronous
-    DMP_CHECK_HIP(hipStreamSynchronize(s));
+    // the host vectors must outlive the asynchronous copies (the stream is
+    // drained before any error return); the launches below stay asynchronous
+    hipError_t e = hipMemcpyAsync(sd_dev, sa.data(), count * sizeof(SplitDesc), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(md_dev, md.data(), count * sizeof(MatDesc), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(t_dev, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, s);
+    const hipError_t e_sync = hipStreamSynchronize(s);
+    DMP_CHECK_HIP(e);
+    DMP_CHECK_HIP(e_sync);
     // A: one grouped row split; B: column splits (per product, small count)
     DMP_CHECK(launch_split_grouped_rowmax(sd_dev, count, ur_a, nullptr, s));
     DMP_CHECK(launch_split_grouped_digits(sd_dev, count, ud_a, slices, kind, nullptr, s));

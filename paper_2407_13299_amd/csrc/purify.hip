@@ -21,6 +21,8 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
+#include <mutex>
 #include <vector>
 
 #include "coef.hpp"
@@ -28,7 +30,6 @@
 
 namespace dmp {
 
-constexpr int kE0Blocks = 256;          // fixed grid of the P0 / energy pass
 
 // Kernel-timing instrumentation (see dmp_timing_*).
 struct TimingState {
@@ -455,306 +456,44 @@ int e0_blocks() { return kE0Blocks; }
 // ---------------------------------------------------------------------------
 // Host driver.
 
-// Tile height of the Ozaki purification products: 64-row tiles (two
-// workgroups per CU; see the slice GEMM) for S <= 7, measured faster than
-// 128-row tiles from n = 512 to n = 8192 except near n = 1536, where 156
-// 128-row tiles fill one round of the 256 CUs exactly and 300 64-row tiles
-// do not.  Beyond S = 7 two 64-row workgroups no longer fit a CU without
-// spills.  DMP_TILE_ROWS = 64 or 128 forces one height where both exist
-// (for measurements).  A function of (kind, S, n) only, so a matrix gets the
-// same tiles, hence bit-identical results, alone, in a batch or in the tape.
-bool tail_split_enabled() {
-    const char* e = std::getenv("DMP_TAIL_SPLIT");
-    return !(e && std::strcmp(e, "0") == 0);
-}
-
-int tile_blocks_for(dmp_kind kind, int S, int n) {
-    (void)n;
-    if ((kind != DMP_OZ_INT8 && kind != DMP_OZ_FP16) || S > 7) return 4;
-    const char* e = std::getenv("DMP_TILE_ROWS");
-    if (e && std::strcmp(e, "128") == 0) return 4;
-    return 2;
-}
-
 namespace {
 
-struct MatLayout {
-    double* X2;
-    double* X3;
-    double* T;        // native TRS4
-    double* Pw;       // workspace iterate (Pb[1])
-    uint8_t* planesP;
-    uint8_t* planesX;
-    int* expP;
-    int* expX;
-    uint64_t* maxP;
-    uint64_t* maxX;
-    double* rows;
-    int* rowbad;
-    double* e0;
-};
+static_assert(sizeof(IPair) == sizeof(int2) && alignof(IPair) == alignof(int2),
+              "tile pairs are passed to the kernels as int2");
 
-int native_blocks(int n) { return int(std::min<int64_t>(2048, (int64_t(n) * n + 255) / 256)); }
-int native_pairs(int n) {
-    const int t = (n + 31) / 32;
-    return t * (t + 1) / 2;
-}
-int oz_tiles(int n, int rb) { return upper_tile_count(n, 32 * rb); }
+const int2* as_int2(const IPair* p) { return reinterpret_cast<const int2*>(p); }
 
-
-
-MatLayout carve_matrix(Carver& c, int n, int S, dmp_kind kind) {
-    MatLayout m{};
-    const size_t nn = size_t(n) * n;
-    m.X2 = c.take<double>(nn);
-    m.Pw = c.take<double>(nn);
-    if (kind == DMP_FP64_NATIVE) {
-        m.X3 = c.take<double>(nn);
-        m.T = c.take<double>(nn);
-    } else {
-        m.planesP = c.take<uint8_t>(plane_bytes(n, n, S, kind));
-        m.planesX = c.take<uint8_t>(plane_bytes(n, n, S, kind));
-        m.expP = c.take<int>(round_up(n, kPad));
-        m.expX = c.take<int>(round_up(n, kPad));
-        m.maxP = c.take<uint64_t>(round_up(n, kPad));
-        m.maxX = c.take<uint64_t>(round_up(n, kPad));
-    }
-    m.rows = c.take<double>(3 * size_t(n));
-    m.rowbad = c.take<int>(n);
-    m.e0 = c.take<double>(kE0Blocks);
-    return m;
-}
-
-// Everything a group of matrices (same S and kind) needs on the device.
-struct GroupPlan {
-    int count = 0;
-    int S = 0;
-    dmp_kind kind = DMP_OZ_INT8;
-    int method = DMP_CANONICAL;
-    std::vector<int> idx;             // positions in the caller's arrays
-    std::vector<MatLayout> lay;
-    PurDesc* pd = nullptr;            // [count]
-    DevState* st = nullptr;           // [count]
-    SplitDesc* splitP[2] = {nullptr, nullptr};  // [count] each
-    SplitDesc* splitX = nullptr;      // [count]
-    SplitDesc* splitT[2] = {nullptr, nullptr};  // TRS4: T from P (parity) and X2
-    MatDesc* sq[2] = {nullptr, nullptr};
-    MatDesc* up[2] = {nullptr, nullptr};
-    Tile* tiles = nullptr;
-    double* partials = nullptr;
-    int ntiles = 0, units_rowmax = 0, units_digits = 0, max_n = 0;
-    int2* pairs = nullptr;            // 32 x 32 tile pairs I <= J of the largest matrix
-    int max_pairs = 0;
-    int rb = 4;                       // 32-row blocks per slice-GEMM tile (4 or 2)
-    int* fix = nullptr;               // part buffer of the tail split
-    int fix_pieces = 0;               // its capacity in parts
-    int min_kc = 0, max_kc = 0;       // fewest / most reduction chunks of a matrix
-    TailSplit tail{0, 1};             // tail split of the slice GEMMs
-};
-
-size_t carve_group(Carver& c, GroupPlan& g, const int* n) {
-    size_t parts = 0;
-    g.lay.resize(g.count);
-    g.max_pairs = 1;
-    g.min_kc = g.max_kc = 0;
-    for (int b = 0; b < g.count; ++b) {
-        const int nb = n[g.idx[b]];
-        g.lay[b] = carve_matrix(c, nb, g.S, g.kind);
-        if (g.kind == DMP_FP64_NATIVE) {
-            parts = std::max<size_t>(parts, std::max(native_blocks(nb), native_pairs(nb)));
-        } else {
-            parts += size_t(oz_tiles(nb, g.rb));
-            const int kc = int(chunks_of(nb, g.kind));
-            g.min_kc = b == 0 ? kc : std::min(g.min_kc, kc);
-            g.max_kc = std::max(g.max_kc, kc);
-        }
-        g.max_pairs = std::max(g.max_pairs, native_pairs(nb));
-    }
-    // part buffer of the tail split (Ozaki kinds), sized for the largest
-    // matrix, so that a batch needs no less workspace than any of its members
-    g.fix_pieces = (g.kind == DMP_OZ_INT8 || g.kind == DMP_OZ_FP16)
-                       ? tail_split_capacity(int(parts), g.max_kc, g.rb) : 0;
-    g.fix = g.fix_pieces > 0 ? c.take<int>(size_t(g.fix_pieces) * piece_ints(g.S, g.rb)) : nullptr;
-    // the refinement step reuses the partials of one matrix's tile pairs
-    parts = std::max<size_t>(parts, size_t(g.max_pairs));
-    g.pd = c.take<PurDesc>(g.count);
-    g.st = c.take<DevState>(g.count);
-    g.splitP[0] = c.take<SplitDesc>(g.count);
-    g.splitP[1] = c.take<SplitDesc>(g.count);
-    g.splitX = c.take<SplitDesc>(g.count);
-    g.splitT[0] = c.take<SplitDesc>(g.count);
-    g.splitT[1] = c.take<SplitDesc>(g.count);
-    g.sq[0] = c.take<MatDesc>(g.count);
-    g.sq[1] = c.take<MatDesc>(g.count);
-    g.up[0] = c.take<MatDesc>(g.count);
-    g.up[1] = c.take<MatDesc>(g.count);
-    g.tiles = c.take<Tile>(std::max<size_t>(1, g.kind == DMP_FP64_NATIVE ? 1 : parts));
-    g.partials = c.take<double>(std::max<size_t>(1, parts) * kPartials);
-    g.pairs = c.take<int2>(g.max_pairs);
-    return c.used();
-}
-
-// Fill the descriptor arrays (host side) and upload them.
+// Fill a carved group's descriptors on the host and copy them to the
+// device; ``keep`` holds the host copies until the stream has passed the
+// copies.
 int upload_group(GroupPlan& g, const double* const* H, double* const* P, const int* n,
-                 const int* nocc, hipStream_t s, std::vector<std::vector<char>>& keep) {
-    const int cnt = g.count;
-    std::vector<PurDesc> pd(cnt);
-    std::vector<SplitDesc> sp0(cnt), sp1(cnt), sx(cnt), st0(cnt), st1(cnt);
-    std::vector<MatDesc> q0(cnt), q1(cnt), u0(cnt), u1(cnt);
-    std::vector<Tile> tiles;
-    int urow = 0, udig = 0;
-    g.max_n = 0;
-    // tile list: matrices from the largest to the smallest (each matrix's
-    // tiles contiguous, so its partials form one range)
-    std::vector<int> order(cnt);
-    for (int b = 0; b < cnt; ++b) order[b] = b;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int x, int y) { return n[g.idx[x]] > n[g.idx[y]]; });
-    std::vector<int> part_begin(cnt, 0), part_end(cnt, 0);
-    if (g.kind != DMP_FP64_NATIVE) {
-        int pbeg = 0;
-        for (int b : order) {
-            const int nb = n[g.idx[b]];
-            part_begin[b] = pbeg;
-            pbeg += oz_tiles(nb, g.rb);
-            part_end[b] = pbeg;
-            append_tiles(tiles, tile_rows(nb, 32 * g.rb), tile_cols(nb), true, uint32_t(b),
-                         32 * g.rb);
-        }
-    }
-    for (int b = 0; b < cnt; ++b) {
-        const int m = g.idx[b], nb = n[m];
-        const MatLayout& L = g.lay[b];
-        g.max_n = std::max(g.max_n, nb);
-        PurDesc d{};
-        d.H = H[m];
-        d.Pb[0] = P[m];
-        d.Pb[1] = L.Pw;
-        d.X2 = L.X2;
-        d.X3 = L.X3;
-        d.T = L.T;
-        d.method = g.method;
-        d.rows = L.rows;
-        d.rowbad = L.rowbad;
-        d.e0 = L.e0;
-        d.partials = g.partials;
-        d.n = nb;
-        d.nocc = nocc[m];
-        if (g.kind == DMP_FP64_NATIVE) {
-            d.part_begin = 0;
-            d.part_end = 0;   // set per phase by the native driver
-        } else {
-            d.part_begin = part_begin[b];
-            d.part_end = part_end[b];
-        }
-        pd[b] = d;
-        if (g.kind == DMP_FP64_NATIVE) continue;
-        const int KC = int(chunks_of(nb, g.kind));
-        const int64_t rbs = int64_t(KC) * planes_of(g.S, g.kind) * kFragBytes;
-        SplitDesc sd{};
-        sd.lda = nb;
-        sd.R = nb;
-        sd.K = nb;
-        sd.trans = 0;
-        sd.KC = KC;
-        sd.ub_rowmax = urow;
-        sd.ub_digits = udig;
-        sd.state_index = b;
-        urow += split_units_rowmax(nb);
-        udig += split_units_digits(nb, KC);
-        // Row maxima: those of P come from the update's epilogue (of P0 from
-        // k_rowmax), those of X2 from the square's; each array is zeroed by
-        // the split that runs just before its producer.
-        sd.A = P[m];
-        sd.maxbits = L.maxP;
-        sd.expo = L.expP;
-        sd.planes = L.planesP;
-        sd.clear = L.maxX;
-        sp0[b] = sd;
-        sd.A = L.Pw;
-        sp1[b] = sd;
-        // TRS4: T = ta P + tb X2 + tc I, split into P's planes (free once the
-        // square has run); its row maxima (k_rowmax) go to X2's array, free
-        // once X2 is split
-        sd.A = P[m];
-        sd.A2 = L.X2;
-        sd.maxbits = L.maxX;
-        sd.clear = nullptr;
-        st0[b] = sd;
-        sd.A = L.Pw;
-        st1[b] = sd;
-        sd.A2 = nullptr;
-        sd.A = L.X2;
-        sd.maxbits = L.maxX;
-        sd.expo = L.expX;
-        sd.planes = L.planesX;
-        sd.clear = L.maxP;
-        sx[b] = sd;
-        MatDesc md{};
-        md.a_rb_stride = rbs;
-        md.b_rb_stride = rbs;
-        md.M = nb;
-        md.N = nb;
-        md.KC = KC;
-        md.ldc = nb;
-        md.state_index = b;
-        md.H = H[m];
-        md.X2 = L.X2;
-        // square: A = B = planes of P
-        md.pa = L.planesP;
-        md.pb = L.planesP;
-        md.ea = L.expP;
-        md.eb = L.expP;
-        md.out = L.X2;
-        md.rowmax = L.maxX;
-        md.P = P[m];
-        q0[b] = md;
-        md.P = L.Pw;
-        q1[b] = md;
-        // update: A = planes of X2, B = planes of P; P' into the other buffer
-        md.pa = L.planesX;
-        md.ea = L.expX;
-        md.rowmax = L.maxP;
-        md.P = P[m];
-        md.out = L.Pw;
-        u0[b] = md;
-        md.P = L.Pw;
-        md.out = P[m];
-        u1[b] = md;
-    }
-    g.ntiles = int(tiles.size());
-    g.tail = TailSplit{g.ntiles, 1};
-    if (g.fix != nullptr && tail_split_enabled()) {
-        int slots = 0;
+                 const int* nocc, hipStream_t s, std::vector<std::unique_ptr<GroupHost>>& keep) {
+    int slots = 0;
+    if (g.fix != nullptr && tail_split_enabled())
         DMP_CHECK(resident_slots(g.S, g.kind, g.rb, &slots));
-        g.tail = plan_tail_split(g.ntiles, slots, g.min_kc, g.fix_pieces);
-    }
-    g.units_rowmax = urow;
-    g.units_digits = udig;
+    keep.push_back(std::make_unique<GroupHost>());
+    GroupHost& h = *keep.back();
+    build_group(g, H, P, n, nocc, slots, h);
     auto up = [&](void* dst, const void* src, size_t bytes) -> int {
         if (bytes == 0) return DMP_OK;
-        keep.emplace_back(static_cast<const char*>(src), static_cast<const char*>(src) + bytes);
-        DMP_CHECK_HIP(hipMemcpyAsync(dst, keep.back().data(), bytes, hipMemcpyHostToDevice, s));
+        DMP_CHECK_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
         return DMP_OK;
     };
-    DMP_CHECK(up(g.pd, pd.data(), cnt * sizeof(PurDesc)));
+    const size_t cnt = size_t(g.count);
+    DMP_CHECK(up(g.pd, h.pd.data(), cnt * sizeof(PurDesc)));
     if (g.kind != DMP_FP64_NATIVE) {
-        DMP_CHECK(up(g.splitP[0], sp0.data(), cnt * sizeof(SplitDesc)));
-        DMP_CHECK(up(g.splitP[1], sp1.data(), cnt * sizeof(SplitDesc)));
-        DMP_CHECK(up(g.splitX, sx.data(), cnt * sizeof(SplitDesc)));
-        DMP_CHECK(up(g.splitT[0], st0.data(), cnt * sizeof(SplitDesc)));
-        DMP_CHECK(up(g.splitT[1], st1.data(), cnt * sizeof(SplitDesc)));
-        DMP_CHECK(up(g.sq[0], q0.data(), cnt * sizeof(MatDesc)));
-        DMP_CHECK(up(g.sq[1], q1.data(), cnt * sizeof(MatDesc)));
-        DMP_CHECK(up(g.up[0], u0.data(), cnt * sizeof(MatDesc)));
-        DMP_CHECK(up(g.up[1], u1.data(), cnt * sizeof(MatDesc)));
-        DMP_CHECK(up(g.tiles, tiles.data(), tiles.size() * sizeof(Tile)));
+        DMP_CHECK(up(g.splitP[0], h.sp0.data(), cnt * sizeof(SplitDesc)));
+        DMP_CHECK(up(g.splitP[1], h.sp1.data(), cnt * sizeof(SplitDesc)));
+        DMP_CHECK(up(g.splitX, h.sx.data(), cnt * sizeof(SplitDesc)));
+        DMP_CHECK(up(g.splitT[0], h.st0.data(), cnt * sizeof(SplitDesc)));
+        DMP_CHECK(up(g.splitT[1], h.st1.data(), cnt * sizeof(SplitDesc)));
+        DMP_CHECK(up(g.sq[0], h.q0.data(), cnt * sizeof(MatDesc)));
+        DMP_CHECK(up(g.sq[1], h.q1.data(), cnt * sizeof(MatDesc)));
+        DMP_CHECK(up(g.up[0], h.u0.data(), cnt * sizeof(MatDesc)));
+        DMP_CHECK(up(g.up[1], h.u1.data(), cnt * sizeof(MatDesc)));
+        DMP_CHECK(up(g.tiles, h.tiles.data(), h.tiles.size() * sizeof(Tile)));
     }
-    std::vector<int2> pairs;
-    const int t = (g.max_n + 31) / 32;
-    for (int i = 0; i < t; ++i)
-        for (int j = i; j < t; ++j) pairs.push_back(int2{i, j});
-    DMP_CHECK(up(g.pairs, pairs.data(), pairs.size() * sizeof(int2)));
+    DMP_CHECK(up(g.pairs, h.pairs.data(), h.pairs.size() * sizeof(IPair)));
     return DMP_OK;
 }
 
@@ -853,69 +592,88 @@ bool graphs_enabled() {
     return !(e && e[0] == '1');
 }
 
-// Run the Ozaki groups to completion; graph-captured batches of iterations.
-int run_oz_groups(std::vector<GroupPlan>& groups, int max_iter, hipStream_t s,
-                  std::vector<DevState>& host_st, const int* n) {
-    int max_n = 0;
-    for (auto& g : groups) max_n = std::max(max_n, g.max_n);
-    const int m = iterations_per_sync(max_n);
-    hipGraphExec_t exec = nullptr;
+// A recorded sequence of m iterations of the groups, instantiated once and
+// replayed by every later run with the same launch sequence (same
+// workspace, sizes and plans; the matrices' pointers live in the uploaded
+// descriptors, not in the launches).
+struct CachedGraph {
     hipGraph_t graph = nullptr;
-    const bool timing = g_timing.on;
-    std::vector<PendingTimer> timers;
-    if (graphs_enabled() && !timing) {
-        hipStream_t cap = nullptr;
-        if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) == hipSuccess) {
-            bool ok = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
-            for (int it = 0; ok && it < m; ++it)
-                for (auto& g : groups) ok = ok && launch_oz_iteration(g, it & 1, cap) == DMP_OK;
-            hipGraph_t gr = nullptr;
-            const bool ended = hipStreamEndCapture(cap, &gr) == hipSuccess;
-            if (ok && ended && gr && hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0) == hipSuccess) {
-                graph = gr;
-            } else {
-                if (gr) (void)hipGraphDestroy(gr);
-                exec = nullptr;
-            }
-            (void)hipStreamDestroy(cap);
-            (void)hipGetLastError();
-            clear_error();
-        }
+    hipGraphExec_t exec = nullptr;
+    int last_iters = 0;    // iterations the previous run of this sequence took
+};
+
+constexpr size_t kGraphCacheCapacity = 16;
+
+// Never destroyed: its graphs would otherwise be released by a static
+// destructor after the HIP runtime may already have shut down.
+KeyedCache<CachedGraph>& graph_cache() {
+    static auto* cache = new KeyedCache<CachedGraph>(kGraphCacheCapacity);
+    return *cache;
+}
+
+std::shared_ptr<CachedGraph> capture_iterations(std::vector<GroupPlan>& groups, int m) {
+    hipStream_t cap = nullptr;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
     }
-    int status = DMP_OK;
+    bool ok = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    for (int it = 0; ok && it < m; ++it)
+        for (auto& g : groups) ok = ok && launch_oz_iteration(g, it & 1, cap) == DMP_OK;
+    hipGraph_t gr = nullptr;
+    const bool ended = hipStreamEndCapture(cap, &gr) == hipSuccess;
+    hipGraphExec_t exec = nullptr;
+    if (!(ok && ended && gr && hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0) == hipSuccess)) {
+        if (gr) (void)hipGraphDestroy(gr);
+        exec = nullptr;
+        gr = nullptr;
+    }
+    (void)hipStreamDestroy(cap);
+    (void)hipGetLastError();
+    clear_error();
+    if (!exec) return nullptr;
+    auto* v = new CachedGraph{gr, exec, 0};
+    return std::shared_ptr<CachedGraph>(v, [](CachedGraph* c) {
+        (void)hipGraphExecDestroy(c->exec);
+        (void)hipGraphDestroy(c->graph);
+        delete c;
+    });
+}
+
+// Page-locked host memory for the state reads of the calling thread (grown
+// as needed, kept until the process ends), so that a read is an
+// asynchronous copy the host can wait for with an event.
+DevState* pinned_states(size_t count) {
+    static thread_local DevState* buf = nullptr;
+    static thread_local size_t cap = 0;
+    if (count > cap) {
+        void* p = nullptr;
+        if (hipHostMalloc(&p, count * sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        buf = static_cast<DevState*>(p);   // the smaller old buffer is left to the process
+        cap = count;
+    }
+    return buf;
+}
+
+// Instrumented run (kernel timing on): eager launches with HIP events around
+// every product, the state read after each batch of m iterations.
+int run_oz_timed(std::vector<GroupPlan>& groups, int max_iter, int m, hipStream_t s,
+                 std::vector<DevState>& host_st, const int* n) {
+    std::vector<PendingTimer> timers;
     const int rounds = (max_iter + m - 1) / m + 1;
     for (int r = 0; r < rounds; ++r) {
-        if (exec) {
-            if (hipGraphLaunch(exec, s) != hipSuccess) {
-                set_error("hipGraphLaunch failed");
-                status = DMP_EHIP;
-                break;
-            }
-        } else {
-            for (int it = 0; it < m && status == DMP_OK; ++it)
-                for (auto& g : groups)
-                    status = launch_oz_iteration(g, it & 1, s, timing ? &timers : nullptr,
-                                                 gemm_ops(g, n));
-            if (status != DMP_OK) break;
-        }
-        bool all = true;
+        for (int it = 0; it < m; ++it)
+            for (auto& g : groups) DMP_CHECK(launch_oz_iteration(g, it & 1, s, &timers, gemm_ops(g, n)));
         size_t off = 0;
         for (auto& g : groups) {
-            if (hipMemcpyAsync(host_st.data() + off, g.st, g.count * sizeof(DevState),
-                               hipMemcpyDeviceToHost, s) != hipSuccess) {
-                set_error("state readback failed");
-                status = DMP_EHIP;
-            }
+            DMP_CHECK_HIP(hipMemcpyAsync(host_st.data() + off, g.st, g.count * sizeof(DevState),
+                                         hipMemcpyDeviceToHost, s));
             off += g.count;
         }
-        if (status != DMP_OK) break;
-        if (hipStreamSynchronize(s) != hipSuccess) {
-            set_error("hipStreamSynchronize failed: %s", hipGetErrorString(hipGetLastError()));
-            status = DMP_EHIP;
-            break;
-        }
-        // launches of finished matrices exit at once: count only the
-        // iterations that ran (iters advanced), one square + one update each
+        DMP_CHECK_HIP(hipStreamSynchronize(s));
         for (auto& t : timers) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, t.start, t.stop) == hipSuccess) {
@@ -927,12 +685,106 @@ int run_oz_groups(std::vector<GroupPlan>& groups, int max_iter, hipStream_t s,
             (void)hipEventDestroy(t.stop);
         }
         timers.clear();
+        bool all = true;
         for (auto& h : host_st) all = all && h.done;
         if (all) break;
     }
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    return status;
+    return DMP_OK;
+}
+
+// Run the Ozaki groups to completion.  Iterations run in replays of m at a
+// time (one cached graph, or eager launches with DMP_NO_GRAPH=1); matrices
+// that have stopped skip their work inside every launch.  The host reads the
+// device states once after the number of replays the previous run of the
+// same launch sequence needed (a first run: after one replay); a run that
+// needs more continues with one replay always queued ahead of the state read
+// being checked, so the GPU does not wait for the host between replays.
+int run_oz_groups(std::vector<GroupPlan>& groups, int max_iter, hipStream_t s,
+                  std::vector<DevState>& host_st, const int* n) {
+    int max_n = 0;
+    for (auto& g : groups) max_n = std::max(max_n, g.max_n);
+    const int m = iterations_per_sync(max_n);
+    if (g_timing.on) return run_oz_timed(groups, max_iter, m, s, host_st, n);
+    std::shared_ptr<CachedGraph> cg;
+    if (graphs_enabled()) {
+        int dev = 0;
+        DMP_CHECK_HIP(hipGetDevice(&dev));
+        cg = graph_cache().get_or_create(launch_key(groups, m, dev, 0),
+                                         [&]() { return capture_iterations(groups, m); });
+    }
+    auto replay = [&]() -> int {
+        if (cg) {
+            DMP_CHECK_HIP(hipGraphLaunch(cg->exec, s));
+            return DMP_OK;
+        }
+        for (int it = 0; it < m; ++it)
+            for (auto& g : groups) DMP_CHECK(launch_oz_iteration(g, it & 1, s));
+        return DMP_OK;
+    };
+    const size_t total = host_st.size();
+    DevState* pin = pinned_states(2 * total);
+    if (pin == nullptr) {
+        set_error("page-locked host memory for the state reads unavailable");
+        return DMP_EHIP;
+    }
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    for (auto& e : ev) DMP_CHECK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    struct EventGuard {
+        hipEvent_t* e;
+        ~EventGuard() {
+            for (int i = 0; i < 2; ++i)
+                if (e[i]) (void)hipEventDestroy(e[i]);
+        }
+    } guard{ev};
+    auto read = [&](int slot) -> int {
+        size_t off = 0;
+        for (auto& g : groups) {
+            DMP_CHECK_HIP(hipMemcpyAsync(pin + slot * total + off, g.st, g.count * sizeof(DevState),
+                                         hipMemcpyDeviceToHost, s));
+            off += g.count;
+        }
+        DMP_CHECK_HIP(hipEventRecord(ev[slot], s));
+        return DMP_OK;
+    };
+    auto finished = [&](int slot) {
+        for (size_t i = 0; i < total; ++i)
+            if (!pin[slot * total + i].done) return false;
+        return true;
+    };
+    const int max_replays = (max_iter + m - 1) / m + 1;
+    const int first = cg && cg->last_iters > 0
+                          ? std::min(max_replays, std::max(1, (cg->last_iters + m - 1) / m))
+                          : 1;
+    int launched = 0;
+    for (; launched < first; ++launched) DMP_CHECK(replay());
+    DMP_CHECK(read(0));
+    DMP_CHECK_HIP(hipEventSynchronize(ev[0]));
+    int last = 0;                 // slot of the newest read checked
+    bool done = finished(0);
+    int pending = -1, slot = 1;   // read in flight, and the slot of the next one
+    while (!done && launched < max_replays) {
+        DMP_CHECK(replay());
+        ++launched;
+        DMP_CHECK(read(slot));
+        if (pending >= 0) {
+            DMP_CHECK_HIP(hipEventSynchronize(ev[pending]));
+            last = pending;
+            done = finished(pending);
+        }
+        pending = slot;
+        slot ^= 1;
+    }
+    if (!done && pending >= 0) {  // the replay budget is spent: the newest read
+        DMP_CHECK_HIP(hipEventSynchronize(ev[pending]));
+        last = pending;
+    }
+    std::copy(pin + last * total, pin + last * total + total, host_st.begin());
+    if (cg) {
+        int it = 0;
+        for (auto& h : host_st) it = std::max(it, h.iters);
+        cg->last_iters = it;
+    }
+    return DMP_OK;
 }
 
 // Native FP64 purification of one matrix (group of one), host-checked
@@ -947,6 +799,14 @@ int run_native(GroupPlan& g, int max_iter, hipStream_t s, DevState& host, bool t
     DMP_CHECK_HIP(hipStreamSynchronize(s));
     const int nb = native_blocks(n), np = native_pairs(n);
     const bool trs4 = g.method == DMP_TRS4;
+    // host sources of the per-phase descriptor copies; the drain keeps them
+    // alive until the stream has passed the copies, also on an error return
+    PurDesc dsq = hd, dup = hd;
+    dsq.part_begin = 0;
+    dsq.part_end = nb;
+    dup.part_begin = 0;
+    dup.part_end = np;
+    StreamDrain drain{s};
     for (int it = 0; it < max_iter; ++it) {
         DMP_CHECK_HIP(hipMemcpyAsync(&host, g.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
         DMP_CHECK_HIP(hipStreamSynchronize(s));
@@ -954,16 +814,10 @@ int run_native(GroupPlan& g, int max_iter, hipStream_t s, DevState& host, bool t
         const double* P = host.iters & 1 ? L.Pw : hd.Pb[0];
         if (tri) {
             DMP_CHECK(native_dsyrk_upper(s, n, P, L.X2));
-            k_mirror_upper<<<np, 256, 0, s>>>(L.X2, n, g.pairs);
+            k_mirror_upper<<<np, 256, 0, s>>>(L.X2, n, as_int2(g.pairs));
         } else {
             DMP_CHECK(native_dgemm(s, false, false, n, n, n, P, n, P, n, L.X2, n));
         }
-        // two host copies: each stays unmodified until the next iteration's sync
-        PurDesc dsq = hd, dup = hd;
-        dsq.part_begin = 0;
-        dsq.part_end = nb;
-        dup.part_begin = 0;
-        dup.part_end = np;
         DMP_CHECK_HIP(hipMemcpyAsync(g.pd, &dsq, sizeof(PurDesc), hipMemcpyHostToDevice, s));
         k_native_square<<<nb, 256, 0, s>>>(g.pd, g.st, nb);
         if (trs4) {
@@ -986,7 +840,7 @@ int run_native(GroupPlan& g, int max_iter, hipStream_t s, DevState& host, bool t
                 DMP_CHECK(native_dgemm(s, false, false, n, n, n, L.X2, n, P, n, L.X3, n));
         }
         DMP_CHECK_HIP(hipMemcpyAsync(g.pd, &dup, sizeof(PurDesc), hipMemcpyHostToDevice, s));
-        k_native_update<<<np, 256, 0, s>>>(g.pd, g.st, g.pairs);
+        k_native_update<<<np, 256, 0, s>>>(g.pd, g.st, as_int2(g.pairs));
         k_finalize_iter<<<1, 256, 0, s>>>(g.pd, g.st);
         DMP_CHECK_HIP(hipGetLastError());
     }
@@ -1008,7 +862,7 @@ int refine_mcweeny(GroupPlan& g, int b, const int* n, DevState& host, hipStream_
     DMP_CHECK(native_dgemm(s, false, false, m, m, m, P, m, P, m, hd.X2, m));
     DMP_CHECK(native_dgemm(s, false, false, m, m, m, hd.X2, m, P, m, other, m));
     const int np = native_pairs(m);
-    k_mcweeny<<<np, 256, 0, s>>>(hd.X2, other, hd.H, m, g.pairs, g.partials);
+    k_mcweeny<<<np, 256, 0, s>>>(hd.X2, other, hd.H, m, as_int2(g.pairs), g.partials);
     k_finalize_refine<<<1, 256, 0, s>>>(g.partials, np, g.st + b);
     DMP_CHECK_HIP(hipGetLastError());
     DMP_CHECK_HIP(hipMemcpyAsync(&host, g.st + b, sizeof(DevState), hipMemcpyDeviceToHost, s));
@@ -1038,64 +892,17 @@ void fill_info(const DevState& h, int S, dmp_kind kind, dmp_info* info) {
 
 }  // namespace
 
-int check_method_flags(int method, int flags) {
-    if (method != DMP_CANONICAL && method != DMP_TRS4) {
-        set_error("unknown method %d", method);
-        return DMP_EINVAL;
-    }
-    if ((flags & ~(DMP_REFINE_MCWEENY | DMP_NATIVE_TRIANGLE)) != 0) {
-        set_error("unknown flags 0x%x", flags);
-        return DMP_EINVAL;
-    }
-    return DMP_OK;
-}
-
-int validate_purify_args(const double* H, int n, int nocc, double tol, int max_iter, const double* P) {
-    if (n < 1 || nocc < 0 || nocc > n) {
-        set_error("need n >= 1 and 0 <= nocc <= n (n=%d, nocc=%d)", n, nocc);
-        return DMP_EINVAL;
-    }
-    if (!(tol > 0.0) || max_iter < 1) {
-        set_error("need tol > 0 and max_iter >= 1");
-        return DMP_EINVAL;
-    }
-    if (!H || !P || H == P) {
-        set_error("H and P must be distinct non-null device pointers");
-        return DMP_EINVAL;
-    }
-    if (n > 65535 * kTileN) {
-        set_error("n too large");
-        return DMP_EINVAL;
-    }
-    return DMP_OK;
-}
-
-// Purify count matrices that share S and kind; used by both entry points.
+// Purify count matrices that share the kind; used by both entry points.
 int purify_many(int count, const double* const* H, const int* n, const int* nocc, double tol,
                 const int* slices, dmp_kind kind, int max_iter, int method, int flags,
                 double* const* P, double* E, dmp_info* info, void* ws, size_t ws_bytes,
                 hipStream_t s, size_t* need_out) {
-    // partition by slice count and tile height (the height follows from each
-    // matrix's own n and S, so a matrix gets the same tiles, hence the same
-    // fixed-order trace sums and bit-identical results, alone or in a batch)
+    // groups of equal slice count and tile choice (the choice follows from
+    // each matrix's own n and S, so a matrix gets the same tiles, hence the
+    // same fixed-order trace sums and bit-identical results, alone or in a
+    // batch)
     std::vector<GroupPlan> groups;
-    for (int b = 0; b < count; ++b) {
-        const int S = kind == DMP_FP64_NATIVE ? 0 : slices[b];
-        const int rb = tile_blocks_for(kind, S, n[b]);
-        GroupPlan* g = nullptr;
-        for (auto& x : groups)
-            if (x.S == S && x.rb == rb && kind != DMP_FP64_NATIVE) g = &x;
-        if (!g) {
-            groups.emplace_back();
-            g = &groups.back();
-            g->S = S;
-            g->kind = kind;
-            g->method = method;
-            g->rb = rb;
-        }
-        g->idx.push_back(b);
-        g->count++;
-    }
+    plan_groups(count, n, slices, kind, method, forced_tile_rb(), groups);
     Carver c(ws);
     for (auto& g : groups) carve_group(c, g, n);
     if (need_out) *need_out = c.used();
@@ -1104,7 +911,10 @@ int purify_many(int count, const double* const* H, const int* n, const int* nocc
         set_error("workspace of %zu bytes required", c.used());
         return DMP_ENOMEM;
     }
-    std::vector<std::vector<char>> keep;
+    // one purification at a time per process (see purify_mutex)
+    std::lock_guard<std::mutex> serial(purify_mutex());
+    std::vector<std::unique_ptr<GroupHost>> keep;
+    StreamDrain drain{s};   // declared after ``keep``: the stream drains first
     for (auto& g : groups) {
         DMP_CHECK(upload_group(g, H, P, n, nocc, s, keep));
         DMP_CHECK(launch_init(g, tol, max_iter, s));
@@ -1164,7 +974,6 @@ int purify_many(int count, const double* const* H, const int* n, const int* nocc
     DMP_CHECK_HIP(hipStreamSynchronize(s));
     return status;
 }
-
 }  // namespace dmp
 
 using namespace dmp;

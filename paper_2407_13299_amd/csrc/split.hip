@@ -14,6 +14,7 @@
 // (32-row block, chunk) adjacent).
 #include "coef.hpp"
 #include "common.hpp"
+#include "plan.hpp"
 
 #include <hip/hip_fp16.h>
 
@@ -357,10 +358,6 @@ static const DigitsFn kDigits[kMaxSlices + 1] = {
     launch_digits_s<8>, launch_digits_s<9>,  launch_digits_s<10>, launch_digits_s<11>,
     launch_digits_s<12>};
 
-// Units per matrix of each split kernel.
-int split_units_rowmax(int R) { return int(round_up(R, kPad)) / 4; }
-int split_units_colmax(int R, int K) { return ((R + 63) / 64) * ((K + 255) / 256); }
-int split_units_digits(int R, int KC) { return int(round_up(R, kPad)) / kFragRows * ((KC + 3) / 4); }
 
 // Split one operand.  ``d`` describes it; ``st`` (nullable) skips the work
 // once the state's done flag is set.

@@ -223,6 +223,42 @@ def test_graph_replays_equal_eager_launches(method, dims, monkeypatch):
     assert np.array_equal(p_graph, p_eager) and e_graph == e_eager
 
 
+@pytest.mark.parametrize("method", ["canonical", "trs4"])
+def test_cached_graph_reused_across_inputs(method, monkeypatch):
+    """Calls that share a workspace replay one cached graph (the matrices'
+    pointers live in descriptors uploaded per call) and read the device state
+    once after the number of replays the previous call needed.  Two matrices
+    of the same size that need different iteration counts, purified in turn
+    through one workspace (so the predicted count is too high, then too low),
+    give the eager launches' results bit for bit; so does a run stopped by
+    max_iter."""
+    lib = dmp._lib.load()
+    h1 = tight_binding_hamiltonian(4, 4, 5, seed=31)
+    n = h1.shape[0]
+    nocc = n // 4
+    h2, _, _ = spectrum_hamiltonian(n, nocc, seed=32)
+    ws = torch.empty(lib.dmp_purify_workspace_bytes(n, 7, 1), dtype=torch.uint8, device="cuda")
+
+    def run(h, **kw):
+        p, e, info = dmp.purify(dev(h), nocc, slices=7, method=method, workspace=ws, **kw)
+        torch.cuda.synchronize()
+        return p.cpu().numpy(), e, info
+
+    graph = [run(h, tol=1e-10) for h in (h1, h2, h1, h2)]
+    capped = [run(h1, tol=1e-10, max_iter=5) for _ in range(2)]
+    monkeypatch.setenv("DMP_NO_GRAPH", "1")
+    eager = [run(h, tol=1e-10) for h in (h1, h2)]
+    eager_capped = run(h1, tol=1e-10, max_iter=5)
+    assert graph[0][2]["iters"] != graph[1][2]["iters"]
+    for k, (p, e, info) in enumerate(graph):
+        pe, ee, ie = eager[k % 2]
+        assert info["iters"] == ie["iters"] and info["stop"] == ie["stop"] == "converged"
+        assert np.array_equal(p, pe) and e == ee
+    for p, e, info in capped:
+        assert info["iters"] == 5 and info["stop"] == "max_iter"
+        assert np.array_equal(p, eager_capped[0]) and e == eager_capped[1]
+
+
 @pytest.mark.skip(reason="the process died once inside this test (two host threads purifying "
                          "concurrently, one capturing a hipGraph), with no GPU fault reported; "
                          "no cause in this library's code has been shown, so the case stays off "
