@@ -44,6 +44,15 @@
  *     still written.
  *   - Determinism: no floating-point atomics; identical inputs give
  *     bitwise-identical outputs on the same device.
+ *   - Threads: the purification entry points (dmp_purify*, the batched and
+ *     taped variants and dmp_purify_bwd) take one process-wide lock, so
+ *     purifications from several host threads run one after another.  The
+ *     GEMM entry points take no lock.  Calls that share a workspace must not
+ *     overlap.
+ *   - Purification runs with the same workspace, sizes, kind, slice count
+ *     and method replay one recorded launch sequence (a hipGraph, kept per
+ *     device for the life of the process, at most 16); the device state is
+ *     read once after as many iterations as the previous such run needed.
  */
 #ifndef DMP_H
 #define DMP_H
