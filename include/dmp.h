@@ -158,6 +158,26 @@ int dmp_ozaki_gemm(char transA, char transB, int m, int n, int k,
                    double* C, int ldc, int slices, dmp_kind kind,
                    void* ws, size_t ws_bytes, void* stream);
 
+/* Allocation-free variant of dmp_ozaki_gemm, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  Same arguments, result and
+ * asynchrony as dmp_ozaki_gemm with kind DMP_OZ_INT8, DMP_OZ_FP16 or
+ * DMP_MARKIDIS_FP16 (DMP_FP64_NATIVE returns DMP_EINVAL), but no workspace:
+ * the digit planes, exponents, maxima and tile list live in a 64 MiB array
+ * that the library holds on every GPU it runs on until the process ends.
+ * A product whose scratch exceeds it returns DMP_EINVAL with the size it
+ * needs (it holds m = n = k = 2048 at S <= 7, about plane bytes
+ * (m + n) k S plus a few arrays; FP16 planes take twice that).  All tiles
+ * run whole (no split tail).  The call makes no allocation (no hipMalloc,
+ * hipFree or allocating library routine).  Every call on one GPU shares
+ * that GPU's array: calls that overlap on one GPU (from several streams or
+ * threads) race, so the caller orders them on one stream or serialises
+ * them. */
+int dmp_ozaki_gemm_noalloc(char transA, char transB, int m, int n, int k,
+                           const double* A, int lda, const double* B, int ldb,
+                           double* C, int ldc, int slices, dmp_kind kind,
+                           void* stream);
+
 /* Grouped GEMM: count independent products C_b = A_b B_b (no transposes,
  * row-major, leading dimensions equal to the row lengths), all with the
  * same slices and kind.  The row splits of all A_b and the slice GEMM of all

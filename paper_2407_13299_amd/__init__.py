@@ -6,4 +6,5 @@ library; the first call does, and fails loudly if it has not been built.
 """
 from ._lib import DmpError  # noqa: F401
 from .api import (Purify, PurifyTape, autotune_slices, max_slices, ozaki_gemm,  # noqa: F401
+                  ozaki_gemm_noalloc,
                   ozaki_gemm_batched, purify, purify_batched, version)

@@ -19,7 +19,7 @@ ERRORS = {-1: "DMP_EINVAL", -2: "DMP_ENONFINITE", -3: "DMP_EHIP", -4: "DMP_ENOME
 # Every symbol the public header declares (tests check the export list).
 EXPORTS = [
     "dmp_last_error", "dmp_version", "dmp_max_slices",
-    "dmp_gemm_workspace_bytes", "dmp_ozaki_gemm",
+    "dmp_gemm_workspace_bytes", "dmp_ozaki_gemm", "dmp_ozaki_gemm_noalloc",
     "dmp_gemm_batched_workspace_bytes", "dmp_ozaki_gemm_batched",
     "dmp_purify_workspace_bytes", "dmp_purify", "dmp_purify_ex",
     "dmp_purify_batched_workspace_bytes", "dmp_purify_batched", "dmp_purify_batched_ex",
@@ -68,6 +68,8 @@ _SIGS = {
     "dmp_gemm_workspace_bytes": (_SZ, [_I, _I, _I, _I, _I]),
     "dmp_ozaki_gemm": (_I, [ctypes.c_char, ctypes.c_char, _I, _I, _I, _P, _I, _P, _I, _P, _I,
                             _I, _I, _P, _SZ, _P]),
+    "dmp_ozaki_gemm_noalloc": (_I, [ctypes.c_char, ctypes.c_char, _I, _I, _I, _P, _I, _P, _I,
+                                    _P, _I, _I, _I, _P]),
     "dmp_gemm_batched_workspace_bytes": (_SZ, [_I, _IP, _IP, _IP, _I, _I]),
     "dmp_ozaki_gemm_batched": (_I, [_I, _IP, _IP, _IP, _PP, _PP, _PP, _I, _I, _P, _SZ, _P]),
     "dmp_purify_workspace_bytes": (_SZ, [_I, _I, _I]),

@@ -10,7 +10,7 @@ import torch
 
 from . import _lib
 
-__all__ = ["ozaki_gemm", "ozaki_gemm_batched", "purify", "purify_batched",
+__all__ = ["ozaki_gemm", "ozaki_gemm_noalloc", "ozaki_gemm_batched", "purify", "purify_batched",
            "autotune_slices", "Purify", "PurifyTape", "max_slices", "version"]
 
 
@@ -100,6 +100,34 @@ def ozaki_gemm(A, B, slices=7, kind="int8", trans_a=False, trans_b=False, out=No
                             _stream(stream))
     _lib.check(st, "dmp_ozaki_gemm")
     _keep_for(ws, stream)
+    return out
+
+
+def ozaki_gemm_noalloc(A, B, slices=7, kind="int8", trans_a=False, trans_b=False, out=None,
+                       stream=None):
+    """C = op(A) op(B) through the allocation-free entry point: the library
+    uses its own fixed device scratch instead of a workspace (only the
+    output is allocated here, when ``out`` is None)."""
+    lib = _lib.load()
+    _check_matrix(A, "A")
+    _check_matrix(B, "B")
+    m = A.shape[1] if trans_a else A.shape[0]
+    k = A.shape[0] if trans_a else A.shape[1]
+    kb = B.shape[1] if trans_b else B.shape[0]
+    n = B.shape[0] if trans_b else B.shape[1]
+    if k != kb:
+        raise ValueError(f"inner dimensions differ: {k} vs {kb}")
+    if A.device != B.device:
+        raise ValueError("A and B are on different devices")
+    if out is None:
+        out = torch.empty((m, n), dtype=torch.float64, device=A.device)
+    else:
+        _check_out(out, (m, n), A)
+    st = lib.dmp_ozaki_gemm_noalloc(b"T" if trans_a else b"N", b"T" if trans_b else b"N", m, n,
+                                    k, _ptr(A), max(1, A.shape[1]), _ptr(B), max(1, B.shape[1]),
+                                    _ptr(out), max(1, out.shape[1]), slices, _kind(kind),
+                                    _stream(stream))
+    _lib.check(st, "dmp_ozaki_gemm_noalloc")
     return out
 
 

@@ -20,7 +20,7 @@ LIB = os.path.join(PKG, "libdmp.so")
 ARCH = "gfx950"
 
 SOURCES = ["plan.cpp", "host.cpp", "gemm_api.cpp", "split.hip", "ozgemm.hip", "purify.hip",
-           "batched.cpp", "adjoint.hip"]
+           "batched.cpp", "adjoint.hip", "noalloc.hip"]
 
 
 def hipcc():
