@@ -6,10 +6,11 @@
 // a 64 x 64 tile (see RB below).  The reduction runs in chunks (32 INT8 or
 // 16 FP16 elements); one chunk of a 128 x 64 tile is 6 S fragment blocks of
 // 1 KiB (4 row blocks of the left operand, 2 of the right, S digit planes
-// each; 4 S for 64 x 64), contiguous in HBM per row block.  Loads run two chunks ahead of the MFMA
-// work through two register sets into two LDS buffers, with one barrier per
-// chunk (each step: load chunk c + 2 into the free register set, MFMAs on
-// chunk c from LDS, store chunk c + 1 into the other LDS buffer, barrier).
+// each; 4 S for 64 x 64), contiguous in HBM per row block.  The fragment
+// blocks go from memory straight into LDS (buffer loads with the LDS flag:
+// no register staging, no LDS stores), into three LDS stages (128-row
+// tiles: chunk c + 2 is loaded while chunk c is multiplied) or two (64-row
+// tiles, two workgroups per CU: chunk c + 1), with one barrier per chunk.
 // Every wavefront forms all S (S + 1) / 2 slice pairs (i + j <= S + 1):
 //   INT8: v_mfma_i32_32x32x32_i8, exact INT32 sums; one accumulator per
 //         anti-diagonal group g = i + j (products of the same weight
@@ -48,24 +49,67 @@ typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 
 // Workgroup barrier without the memory fence __syncthreads() implies (that
 // fence would also wait for the prefetch loads in flight); the signal fences
-// keep the compiler from moving memory accesses across it, and LDS
-// visibility is ordered by the explicit lgkmcnt(0) before each barrier.
+// keep the compiler from moving memory accesses across it.  Before each
+// barrier the kernel waits for its own operand loads and LDS reads itself
+// (ops_wait).
 __device__ inline void bare_barrier() {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __builtin_amdgcn_s_barrier();
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-// s_waitcnt lgkmcnt(0) (gfx9 encoding: vmcnt and expcnt fields at their
-// maximum, i.e. not waited on)
-__device__ inline void wait_lgkm0() {
-    __builtin_amdgcn_s_waitcnt(0xc07f);
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
-
 // Fourth word of a raw buffer descriptor on gfx950 (32-bit data format,
 // no swizzle, no index stride).
 constexpr int kBufferWord3 = 0x00020000;
+
+typedef __attribute__((address_space(3))) uint8_t lds_u8;
+
+// Byte offset of a shared-memory address inside the workgroup's LDS.
+__device__ inline uint32_t lds_offset(const void* p) {
+    return static_cast<uint32_t>(reinterpret_cast<size_t>((const lds_u8*)(p)));
+}
+
+// A raw buffer descriptor (base, no stride, ``bytes`` records) as four
+// wave-uniform words, for the inline assembly below, which takes it in
+// scalar registers.
+__device__ inline v4i sgpr_desc(const void* base, int bytes) {
+    const uint64_t b = reinterpret_cast<uint64_t>(base);
+    v4i d;
+    d[0] = __builtin_amdgcn_readfirstlane(int(uint32_t(b)));
+    d[1] = __builtin_amdgcn_readfirstlane(int(uint32_t(b >> 32) & 0xffffu));
+    d[2] = __builtin_amdgcn_readfirstlane(bytes);
+    d[3] = kBufferWord3;
+    return d;
+}
+
+// One 1 KiB fragment block from global memory straight into LDS (a buffer
+// load with the LDS flag): lane l's 16 bytes at buffer offset voff + soff
+// land at LDS byte lds + 16 l, which is exactly the fragment layout, so no
+// register staging and no LDS store instruction is needed.  It is written
+// as inline assembly so that the compiler's wait counting, which would
+// otherwise wait for every such load before any LDS read, leaves it alone;
+// the kernel waits for these loads itself (ops_wait) before the barrier
+// that publishes them.  The load has no register destination; m0 holds the
+// LDS address and is set right before it.
+__device__ inline void frag_to_lds(v4i r, uint32_t lds, int voff, int soff) {
+    // the operands are wave-uniform; reading them from the first lane makes
+    // them scalar registers at this point even where register pressure has
+    // moved them to vector registers in between
+    v4i rs;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rs[q] = __builtin_amdgcn_readfirstlane(r[q]);
+    const uint32_t ls = __builtin_amdgcn_readfirstlane(lds);
+    const int ss = __builtin_amdgcn_readfirstlane(soff);
+    asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dwordx4 %1, %2, %3 offen lds"
+                 :: "s"(ls), "v"(voff), "s"(rs), "s"(ss) : "memory", "m0");
+}
+
+// s_waitcnt vmcnt(N) lgkmcnt(0): at most N vector-memory operations of the
+// wavefront still in flight, and every LDS read returned.
+template <int N>
+__device__ inline void ops_wait() {
+    asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)" :: "n"(N) : "memory");
+}
 
 __device__ inline double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -79,7 +123,7 @@ __device__ inline double wave_sum(double v) {
 // otherwise the plain ones (EPI_STORE, EPI_STORE_SYM).  Two instantiations
 // keep each epilogue free of the other family's code.
 // RB: 32-row blocks of the left operand per tile.  RB = 4: 128 x 64 tiles,
-// 8 wavefronts, one workgroup per CU (84 KiB of LDS at S = 7).  RB = 2:
+// 8 wavefronts, one workgroup per CU (126 KiB of LDS at S = 7).  RB = 2:
 // 64 x 64 tiles, 4 wavefronts, 56 KiB, two workgroups per CU, so that one
 // tile's pipeline fill and epilogue overlap another's main loop (small
 // matrices, where those are a large share of a tile's time).
@@ -94,8 +138,11 @@ __global__ __launch_bounds__(128 * RB, RB == 4 ? 1 : 2) void k_ozgemm(GemmParams
     constexpr int BLOCKS = (RB + 2) * S;          // 1 KiB blocks per chunk
     constexpr int STAGE = BLOCKS * kFragBytes;
     constexpr int WAVES = 2 * RB;
-    constexpr int PER = (BLOCKS + WAVES - 1) / WAVES;  // loads per thread per chunk
-    __shared__ __align__(16) uint8_t lds[2][STAGE];
+    constexpr int PER = (BLOCKS + WAVES - 1) / WAVES;  // loads per wavefront per chunk
+    // LDS stages: three for the 128-row tiles (one workgroup per CU) while
+    // they fit, else two (the 64-row tiles keep two workgroups per CU)
+    constexpr int NBUF = RB == 4 && 3 * STAGE <= 150 * 1024 ? 3 : 2;
+    __shared__ __align__(16) uint8_t lds[NBUF][STAGE];
     __shared__ double red[WAVES][kPartials];
 
     static_assert(PHASE == kWhole || TERMS == 0, "tail split: Ozaki kinds");
@@ -138,14 +185,13 @@ __global__ __launch_bounds__(128 * RB, RB == 4 ? 1 : 2) void k_ozgemm(GemmParams
     // Block b of a chunk is digit plane b % S of operand row block b / S (left
     // operand row blocks RB I .. RB I + RB - 1, then right operand row blocks
     // 2J, 2J+1).
-    // Loads are buffer loads: one descriptor per piece holding the base of
-    // its row block (wave-uniform), the per-chunk offset in a scalar register
-    // and the lane's 16 bytes as the only vector offset, so no per-lane
-    // 64-bit address arithmetic runs in the loop.  Every wavefront issues
-    // PER loads per chunk (a block index past the end re-reads block 0 and is
-    // not stored), so the count of loads in flight is the same on every path
-    // and the compiler's waits stay exact.
-    __amdgpu_buffer_rsrc_t rsrc[PER];
+    // Loads are buffer loads straight into LDS: one descriptor per piece
+    // holding the base of its row block (wave-uniform, scalar registers),
+    // the per-chunk offset in a scalar register and the lane's 16 bytes as
+    // the only vector offset.  Pieces past the last block are not loaded:
+    // wavefronts [0, FULL) issue PER loads per chunk, the others PER - 1.
+    constexpr int FULL = BLOCKS - (PER - 1) * WAVES;
+    v4i dsc[PER];
     int poff[PER];
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
@@ -156,22 +202,29 @@ __global__ __launch_bounds__(128 * RB, RB == 4 ? 1 : 2) void k_ozgemm(GemmParams
         const uint8_t* base = ob < RB ? d.pa + int64_t(RB * I + ob) * a_rb
                                       : d.pb + int64_t(2 * J + ob - RB) * b_rb;
         const int64_t rb = ob < RB ? a_rb : b_rb;   // bytes of one row block
-        rsrc[i] = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(base), 0, int(rb),
-                                                    kBufferWord3);
+        dsc[i] = sgpr_desc(base, int(rb));
     }
-    auto gload = [&](int kc, v4i (&r)[PER]) __attribute__((always_inline)) {
-#pragma unroll
-        for (int i = 0; i < PER; ++i)
-            r[i] = __builtin_amdgcn_raw_buffer_load_b128(rsrc[i], lane * 16,
-                                                         kc * (S * kFragBytes) + poff[i], 0);
-    };
-    auto lstore = [&](int buf, const v4i (&r)[PER]) __attribute__((always_inline)) {
+    const uint32_t lbase = lds_offset(&lds[0][0]);
+    // loads of chunk kc into LDS stage ``stage``
+    auto issue = [&](int kc, int stage) __attribute__((always_inline)) {
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const int blk = i * WAVES + wave;
-            if (blk < BLOCKS)
-                *reinterpret_cast<v4i*>(&lds[buf][blk * kFragBytes + lane * 16]) = r[i];
+            if (i < PER - 1 || blk < BLOCKS)
+                frag_to_lds(dsc[i], lbase + uint32_t(stage * STAGE + blk * kFragBytes), lane * 16,
+                            kc * (S * kFragBytes) + poff[i]);
         }
+    };
+    // wait for this wavefront's loads of every chunk but the newest one
+    // (and for its LDS reads), then the barrier
+    const bool full = wave < FULL;
+    auto publish_older = [&]() __attribute__((always_inline)) {
+        if (full) ops_wait<PER>(); else ops_wait<PER - 1>();
+        bare_barrier();
+    };
+    auto publish_all = [&]() __attribute__((always_inline)) {
+        ops_wait<0>();
+        bare_barrier();
     };
 
     static_assert(TERMS == 0 || (S == 2 && FP16), "Markidis: two FP16 planes");
@@ -238,27 +291,6 @@ __global__ __launch_bounds__(128 * RB, RB == 4 ? 1 : 2) void k_ozgemm(GemmParams
         }
     };
 
-    v4i r0[PER], r1[PER];
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        r0[i] = v4i{0, 0, 0, 0};
-        r1[i] = v4i{0, 0, 0, 0};
-    }
-    // One step for chunk kc (kc = -2, -1 fill the pipeline, kc >= KC drain
-    // it): load chunk min(kc + 2, KC - 1) into the free register set, MFMAs
-    // on chunk kc from LDS buffer ``buf`` when 0 <= kc < KC, store the set
-    // loaded one step earlier (chunk kc + 1) into the other buffer, barrier.
-    // Loads and stores are unconditional (clamped, surplus ones are never
-    // read), so the compiler sees the same loads in flight on every path and
-    // its waits are exact: each store waits only for its own loads, while the
-    // next chunk's loads stay in flight.
-    auto step = [&](int kc, int buf, v4i (&fre)[PER], const v4i (&nxt)[PER]) __attribute__((always_inline)) {
-        gload(min(kc + 2, KC - 1), fre);
-        if (kc >= 0 && kc < KC) compute(buf);
-        lstore(buf ^ 1, nxt);
-        wait_lgkm0();
-        bare_barrier();
-    };
     // an update whose product weight is zero (a TRS4 step without the
     // second product) keeps only the elementwise part
     const bool no_product = PUR && p.mode == EPI_UPDATE && st != nullptr && st->gamma == 0.0;
@@ -292,10 +324,39 @@ __global__ __launch_bounds__(128 * RB, RB == 4 ? 1 : 2) void k_ozgemm(GemmParams
             }
         }
     } else {
+        // Chunk c lives in LDS stage c mod NBUF.  Three stages: chunk c + 2
+        // is loaded while chunk c is multiplied, and the barrier ending the
+        // step publishes chunk c + 1.  Two stages: chunk c + 1 is loaded
+        // while chunk c is multiplied and published at the end of the step.
+        // A stage is reloaded only after the barrier that follows the last
+        // reads of the chunk it held.
         if (!no_product && KC > 0) {
-            for (int kc = -2; kc < KC; kc += 2) {
-                step(kc, 0, r0, r1);
-                step(kc + 1, 1, r1, r0);
+            if constexpr (NBUF == 3) {
+                issue(0, 0);
+                if (KC > 1) {
+                    issue(1, 1);
+                    publish_older();
+                } else {
+                    publish_all();
+                }
+                int stage = 0;
+                for (int kc = 0; kc < KC; ++kc) {
+                    const bool more = kc + 2 < KC;
+                    if (more) issue(kc + 2, stage == 0 ? 2 : stage - 1);   // (kc + 2) mod 3
+                    compute(stage);
+                    if (more) publish_older(); else publish_all();
+                    stage = stage == 2 ? 0 : stage + 1;
+                }
+            } else {
+                issue(0, 0);
+                publish_all();
+                int stage = 0;
+                for (int kc = 0; kc < KC; ++kc) {
+                    if (kc + 1 < KC) issue(kc + 1, stage ^ 1);
+                    compute(stage);
+                    publish_all();
+                    stage ^= 1;
+                }
             }
         }
         if constexpr (PHASE == kPiece) {
