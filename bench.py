@@ -51,6 +51,10 @@ def parse():
                     help="iteration cap (short profiled runs use a few)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--calibrate-frag", action="store_true",
+                    help="also run one single-tile slice GEMM that reads 25153536 bytes of "
+                         "digit planes exactly once through the kernel's own loads (counter "
+                         "calibration of the slice GEMM's access pattern)")
     return ap.parse_args()
 
 
@@ -431,6 +435,20 @@ def main():
         print(f"# calibration copy: {a.calibrate_copy} MiB read + written", file=sys.stderr,
               flush=True)
         del src, dst
+
+    if a.calibrate_frag:
+        # one 128 x 64 output tile of C = A B with S = 1 and k = 131008: the
+        # slice GEMM reads the 128 + 64 operand rows of one digit plane,
+        # (128 + 64) x 131008 bytes = 25153536 bytes, once each (no other tile
+        # reuses them); the splits are launches of their own
+        kk = 131072 - 64
+        ga = torch.ones((128, kk), dtype=torch.float64, device="cuda")
+        gb = torch.ones((kk, 64), dtype=torch.float64, device="cuda")
+        dmp.ozaki_gemm(ga, gb, slices=1)
+        torch.cuda.synchronize()
+        print("# calibration GEMM: 25153536 bytes of digit planes read by the slice GEMM",
+              file=sys.stderr, flush=True)
+        del ga, gb
 
     print(f"# workload {a.workload}: n={n} nocc={nocc}; warmup {a.warmup}", file=sys.stderr,
           flush=True)
