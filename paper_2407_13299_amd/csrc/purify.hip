@@ -167,8 +167,14 @@ __global__ __launch_bounds__(256) void k_finalize_init(const PurDesc* pd, DevSta
 
 // P0 = lam (mu I - H) + theta I from the upper triangle of H (mirrored), and
 // partial energies tr(P0 H); fixed grid of kE0Blocks blocks per matrix.
+// Block x takes the 32 x 32 tile pairs (I, J), I <= J, numbered row by row,
+// x, x + kE0Blocks, ...: it reads tile (I, J) of H with coalesced rows,
+// writes P0's tile (I, J) and, transposed through LDS, tile (J, I), also
+// with coalesced rows.  Its energy partial is the sum over the upper
+// elements of (1 or 2) P0_ij H_ij, in a fixed order.
 __global__ __launch_bounds__(256) void k_init_p0(const PurDesc* pd, const DevState* states) {
     __shared__ double sh[4];
+    __shared__ double tileT[32][33];
     const PurDesc& d = pd[blockIdx.y];
     const DevState& s = states[blockIdx.y];
     // locals: the stores to P below could alias the descriptor and the state
@@ -177,16 +183,37 @@ __global__ __launch_bounds__(256) void k_init_p0(const PurDesc* pd, const DevSta
     const double* H = d.H;
     double* P = d.Pb[0];
     const double lam = s.lambda, mu = s.mu, theta = s.theta;
-    const int64_t tot = int64_t(n) * n;
+    const int T = (n + 31) / 32;
+    const int npairs = T * (T + 1) / 2;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     double e = 0.0;
     if (!s.nonfinite) {
-        for (int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x; idx < tot;
-             idx += int64_t(kE0Blocks) * 256) {
-            const int i = int(idx / n), j = int(idx % n);
-            const double h = i <= j ? H[idx] : H[int64_t(j) * n + i];
-            const double p = lam * ((i == j ? mu : 0.0) - h) + (i == j ? theta : 0.0);
-            P[idx] = p;
-            e += p * h;
+        for (int pi = blockIdx.x; pi < npairs; pi += kE0Blocks) {
+            // row I of the pair triangle holds pairs [I T - I (I - 1) / 2, ...)
+            int I = int((2.0 * T + 1.0 - sqrt((2.0 * T + 1.0) * (2.0 * T + 1.0) - 8.0 * pi)) * 0.5);
+            auto first = [&](int r) { return r * T - r * (r - 1) / 2; };
+            if (I > 0 && first(I) > pi) --I;
+            if (I + 1 < T && first(I + 1) <= pi) ++I;
+            const int J = I + (pi - first(I));
+            for (int r = ty; r < 32; r += 8) {
+                const int i = I * 32 + r, j = J * 32 + tx;
+                double p = 0.0;
+                if (i < n && j < n && !(I == J && j < i)) {
+                    const int64_t ij = int64_t(i) * n + j;
+                    const double h = H[ij];
+                    p = lam * ((i == j ? mu : 0.0) - h) + (i == j ? theta : 0.0);
+                    P[ij] = p;
+                    e += (i == j ? 1.0 : 2.0) * p * h;
+                }
+                tileT[r][tx] = p;
+            }
+            __syncthreads();
+            for (int r = ty; r < 32; r += 8) {
+                // element (J 32 + r, I 32 + tx) = tile (I, J)[tx][r]
+                const int i = J * 32 + r, j = I * 32 + tx;
+                if (i < n && j < n && (I != J || j < i)) P[int64_t(i) * n + j] = tileT[tx][r];
+            }
+            __syncthreads();
         }
     }
     e = block_sum(e, sh);
