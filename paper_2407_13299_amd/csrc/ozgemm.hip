@@ -344,6 +344,7 @@ __global__ __launch_bounds__(128 * RB, RB == 4 ? 1 : 2) void k_ozgemm(GemmParams
                     const bool more = kc + 2 < KC;
                     if (more) issue(kc + 2, stage == 0 ? 2 : stage - 1);   // (kc + 2) mod 3
                     compute(stage);
+                    __builtin_amdgcn_sched_barrier(0);   // as in the two-stage loop
                     if (more) publish_older(); else publish_all();
                     stage = stage == 2 ? 0 : stage + 1;
                 }
@@ -354,6 +355,11 @@ __global__ __launch_bounds__(128 * RB, RB == 4 ? 1 : 2) void k_ozgemm(GemmParams
                 for (int kc = 0; kc < KC; ++kc) {
                     if (kc + 1 < KC) issue(kc + 1, stage ^ 1);
                     compute(stage);
+                    // keep every product of the chunk ahead of the barrier
+                    // (the scheduler would otherwise move some past it, so the
+                    // wave would wait at the barrier with little of its own
+                    // work in the matrix core)
+                    __builtin_amdgcn_sched_barrier(0);
                     publish_all();
                     stage ^= 1;
                 }
