@@ -90,7 +90,9 @@ __device__ inline v4i sgpr_desc(const void* base, int bytes) {
 // otherwise wait for every such load before any LDS read, leaves it alone;
 // the kernel waits for these loads itself (ops_wait) before the barrier
 // that publishes them.  The load has no register destination; m0 holds the
-// LDS address and is set right before it.
+// LDS address and is set right before it.  m0 is a register the compiler
+// reserves; nothing else in these kernels reads it (gfx950 LDS instructions
+// do not use it), which tests/test_isa_m0.py checks on the compiled code.
 __device__ inline void frag_to_lds(v4i r, uint32_t lds, int voff, int soff) {
     // the operands are wave-uniform; reading them from the first lane makes
     // them scalar registers at this point even where register pressure has
