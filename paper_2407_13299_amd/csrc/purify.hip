@@ -736,7 +736,9 @@ int run_oz_groups(std::vector<GroupPlan>& groups, int max_iter, hipStream_t s,
     if (graphs_enabled()) {
         int dev = 0;
         DMP_CHECK_HIP(hipGetDevice(&dev));
-        cg = graph_cache().get_or_create(launch_key(groups, m, dev, 0),
+        // the measurement switch is read at capture: part of the key
+        const int env = tail_split_enabled() ? 1 : 0;
+        cg = graph_cache().get_or_create(launch_key(groups, m, dev, env),
                                          [&]() { return capture_iterations(groups, m); });
     }
     auto replay = [&]() -> int {
