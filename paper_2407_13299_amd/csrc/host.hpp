@@ -29,10 +29,12 @@ int launch_split_digits(const SplitDesc& d, int S, dmp_kind kind, const DevState
 int launch_split_grouped_rowmax(const SplitDesc* descs_dev, int count, int units,
                                 const DevState* st, hipStream_t stream);
 // coef.count > 0: the same launch also runs the coefficient step of the
-// matrices (extra blocks ahead of the split's units)
+// matrices (extra blocks ahead of the split's units).  combined: the
+// descriptors hold combined operands (A2 set, every one of them); otherwise
+// none may.
 int launch_split_grouped_digits(const SplitDesc* descs_dev, int count, int units, int S,
                                 dmp_kind kind, const DevState* st, hipStream_t stream,
-                                const CoefArgs& coef = CoefArgs{});
+                                const CoefArgs& coef = CoefArgs{}, bool combined = false);
 
 struct GemmParams;
 // 32-row blocks per slice-GEMM tile (2: 64-row tiles, 4: 128-row tiles) of

@@ -598,7 +598,7 @@ int launch_oz_iteration(GroupPlan& g, int par, hipStream_t s,
     if (trs4) {
         DMP_CHECK(launch_split_grouped_rowmax(g.splitT[par], g.count, g.units_rowmax, g.st, s));
         DMP_CHECK(launch_split_grouped_digits(g.splitT[par], g.count, g.units_digits, g.S, g.kind,
-                                              g.st, s));
+                                              g.st, s, CoefArgs{}, true));
     }
     p.descs = g.up[par];
     p.mode = EPI_UPDATE;

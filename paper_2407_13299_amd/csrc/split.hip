@@ -189,9 +189,12 @@ __device__ inline int exponent_of(uint64_t bits) {
 // rows, which are adjacent in memory.
 // HALVES (Markidis kind, S = 2, FP16): instead of digits, the high and low
 // FP16 parts of x = a 2^-e (|x| < 1): X0 = FP16[x], X1 = FP16[x - X0].
+// COMB: the operand is the combination ta A + tb A2 + tc I (d.A2 set; the
+// TRS4 right operand); an instantiation of its own, so that the plain
+// split keeps the registers of its second staging array free.
 // coef.count > 0: the first coef.count blocks of the grid run the coefficient
 // step of the matrices instead (CoefArgs), beside the split's units.
-template <int S, bool FP16, bool HALVES = false>
+template <int S, bool FP16, bool HALVES = false, bool COMB = false>
 __global__ __launch_bounds__(256) void k_digits(const SplitDesc* descs, int count,
                                                 SplitDesc one, const DevState* st, CoefArgs coef) {
     constexpr int CK = FP16 ? 16 : 32;
@@ -234,7 +237,7 @@ __global__ __launch_bounds__(256) void k_digits(const SplitDesc* descs, int coun
         // are in flight per lane
         const int kb = kq * W;
         double stage[PER];
-        if (d.A2 != nullptr) {
+        if constexpr (COMB) {
             double stage2[PER];
 #pragma unroll
             for (int t = 0; t < PER; ++t) {
@@ -307,51 +310,99 @@ __global__ __launch_bounds__(256) void k_digits(const SplitDesc* descs, int coun
         *reinterpret_cast<uint4*>(base + kFragBytes) = make_uint4(w[1][0], w[1][1], w[1][2], w[1][3]);
         return;
     }
-    int dg[NE][S];
+    // Each element's digits are packed as soon as they are formed (word q
+    // of plane s holds digit s of elements 4 q .. 4 q + 3 for INT8, of 2 q,
+    // 2 q + 1 for FP16), so only the packed words stay live, not all digits
+    // of the lane's elements.
+    uint32_t w[S][4];
+    if constexpr (!FP16 && S <= 8) {
+        // INT8 digits from their integer definition: X = rint(a 2^(8S - 2 - e))
+        // (ties to even; |X| <= 2^(8S - 2) <= 2^62) is the sum of d_s
+        // 2^(8 (S - s)) with d_2 .. d_S in [-128, 127], the same digits the
+        // rounding steps above give (their sum is rint of the same value, and
+        // this balanced representation is unique).  Adding 128 in each of the
+        // S - 1 low bytes makes byte S - s of X + bias equal to d_s + 128
+        // (s >= 2) and the bytes above it d_1; the digit is that byte with
+        // its top bit flipped.  Exact: the scaling is a power of two, the
+        // halves of X below are exact in FP64.
+        constexpr uint64_t kBias = S >= 2 ? 0x8080808080808080ull >> (8 * (9 - S)) : 0ull;
 #pragma unroll
-    for (int i = 0; i < NE; ++i) digits_of<S>(v[i], e, dg[i]);
-
+        for (int i = 0; i < NE; ++i) {
+            const double x = e >= kNonFiniteExp ? 0.0 : rint(ldexp(v[i], 8 * S - 2 - e));
+            const double hi = floor(ldexp(x, -32));
+            const uint32_t lo = uint32_t(__builtin_fma(hi, -4294967296.0, x));
+            const uint64_t u = ((uint64_t(uint32_t(int32_t(hi))) << 32) | lo) + kBias;
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-        uint4 out;
-        if constexpr (!FP16) {
-            uint32_t w[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                w[q] = (uint32_t(uint8_t(dg[4 * q + 0][s]))) |
-                       (uint32_t(uint8_t(dg[4 * q + 1][s])) << 8) |
-                       (uint32_t(uint8_t(dg[4 * q + 2][s])) << 16) |
-                       (uint32_t(uint8_t(dg[4 * q + 3][s])) << 24);
-            out = make_uint4(w[0], w[1], w[2], w[3]);
-        } else {
-            uint32_t w[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                __half lo = __int2half_rn(dg[2 * q][s]);
-                __half hi = __int2half_rn(dg[2 * q + 1][s]);
-                w[q] = uint32_t(__half_as_ushort(lo)) | (uint32_t(__half_as_ushort(hi)) << 16);
+            for (int p = 0; p < S; ++p) {
+                const uint32_t byte = (uint32_t(u >> (8 * (S - 1 - p))) & 0xffu) ^ (p > 0 ? 0x80u : 0u);
+                const uint32_t part = byte << (8 * (i & 3));
+                w[p][i >> 2] = (i & 3) == 0 ? part : (w[p][i >> 2] | part);
             }
-            out = make_uint4(w[0], w[1], w[2], w[3]);
         }
-        *reinterpret_cast<uint4*>(base + int64_t(s) * kFragBytes) = out;
+#pragma unroll
+        for (int p = 0; p < S; ++p)
+            *reinterpret_cast<uint4*>(base + int64_t(p) * kFragBytes) =
+                make_uint4(w[p][0], w[p][1], w[p][2], w[p][3]);
+        return;
     }
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+        int dd[S];
+        digits_of<S>(v[i], e, dd);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            uint32_t part;
+            int q;
+            bool first;
+            if constexpr (!FP16) {
+                part = uint32_t(uint8_t(dd[s])) << (8 * (i & 3));
+                q = i >> 2;
+                first = (i & 3) == 0;
+            } else {
+                part = uint32_t(__half_as_ushort(__int2half_rn(dd[s]))) << (16 * (i & 1));
+                q = i >> 1;
+                first = (i & 1) == 0;
+            }
+            w[s][q] = first ? part : (w[s][q] | part);
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+        *reinterpret_cast<uint4*>(base + int64_t(s) * kFragBytes) =
+            make_uint4(w[s][0], w[s][1], w[s][2], w[s][3]);
 }
 
 // ---------------------------------------------------------------------------
 // Host launchers.
 
 template <int S>
-static void launch_digits_s(bool fp16, const SplitDesc* descs, int count, const SplitDesc& one,
-                            const DevState* st, int units, const CoefArgs& coef,
-                            hipStream_t stream) {
-    if (fp16)
-        k_digits<S, true><<<units + coef.count, 256, 0, stream>>>(descs, count, one, st, coef);
+static void launch_digits_s(bool fp16, bool comb, const SplitDesc* descs, int count,
+                            const SplitDesc& one, const DevState* st, int units,
+                            const CoefArgs& coef, hipStream_t stream) {
+    const unsigned grid = unsigned(units + coef.count);
+    if (fp16 && comb)
+        k_digits<S, true, false, true><<<grid, 256, 0, stream>>>(descs, count, one, st, coef);
+    else if (fp16)
+        k_digits<S, true><<<grid, 256, 0, stream>>>(descs, count, one, st, coef);
+    else if (comb)
+        k_digits<S, false, false, true><<<grid, 256, 0, stream>>>(descs, count, one, st, coef);
     else
-        k_digits<S, false><<<units + coef.count, 256, 0, stream>>>(descs, count, one, st, coef);
+        k_digits<S, false><<<grid, 256, 0, stream>>>(descs, count, one, st, coef);
 }
 
-using DigitsFn = void (*)(bool, const SplitDesc*, int, const SplitDesc&, const DevState*, int,
-                          const CoefArgs&, hipStream_t);
+// The Markidis kind's two FP16 parts (S = 2).
+static void launch_halves(bool comb, const SplitDesc* descs, int count, const SplitDesc& one,
+                          const DevState* st, int units, const CoefArgs& coef,
+                          hipStream_t stream) {
+    const unsigned grid = unsigned(units + coef.count);
+    if (comb)
+        k_digits<2, true, true, true><<<grid, 256, 0, stream>>>(descs, count, one, st, coef);
+    else
+        k_digits<2, true, true><<<grid, 256, 0, stream>>>(descs, count, one, st, coef);
+}
+
+using DigitsFn = void (*)(bool, bool, const SplitDesc*, int, const SplitDesc&, const DevState*,
+                          int, const CoefArgs&, hipStream_t);
 static const DigitsFn kDigits[kMaxSlices + 1] = {
     nullptr,           launch_digits_s<1>,  launch_digits_s<2>,  launch_digits_s<3>,
     launch_digits_s<4>, launch_digits_s<5>,  launch_digits_s<6>,  launch_digits_s<7>,
@@ -371,11 +422,11 @@ int launch_split(const SplitDesc& d, int S, dmp_kind kind, const DevState* st,
         k_fill_u64<<<(rp + 255) / 256, 256, 0, stream>>>(d.maxbits, rp, 0ull);
         if (d.K > 0) k_colmax<<<split_units_colmax(d.R, d.K), 256, 0, stream>>>(nullptr, 0, d, st);
     }
+    const bool comb = d.A2 != nullptr;
     if (kind == DMP_MARKIDIS_FP16)
-        k_digits<2, true, true><<<split_units_digits(d.R, d.KC), 256, 0, stream>>>(nullptr, 0, d, st,
-                                                                                  CoefArgs{});
+        launch_halves(comb, nullptr, 0, d, st, split_units_digits(d.R, d.KC), CoefArgs{}, stream);
     else
-        kDigits[S](kind == DMP_OZ_FP16, nullptr, 0, d, st, split_units_digits(d.R, d.KC),
+        kDigits[S](kind == DMP_OZ_FP16, comb, nullptr, 0, d, st, split_units_digits(d.R, d.KC),
                    CoefArgs{}, stream);
     DMP_CHECK_HIP(hipGetLastError());
     return DMP_OK;
@@ -386,11 +437,11 @@ int launch_split(const SplitDesc& d, int S, dmp_kind kind, const DevState* st,
 int launch_split_digits(const SplitDesc& d, int S, dmp_kind kind, const DevState* st,
                         hipStream_t stream) {
     if (round_up(d.R, kPad) == 0) return DMP_OK;
+    const bool comb = d.A2 != nullptr;
     if (kind == DMP_MARKIDIS_FP16)
-        k_digits<2, true, true><<<split_units_digits(d.R, d.KC), 256, 0, stream>>>(nullptr, 0, d, st,
-                                                                                  CoefArgs{});
+        launch_halves(comb, nullptr, 0, d, st, split_units_digits(d.R, d.KC), CoefArgs{}, stream);
     else
-        kDigits[S](kind == DMP_OZ_FP16, nullptr, 0, d, st, split_units_digits(d.R, d.KC),
+        kDigits[S](kind == DMP_OZ_FP16, comb, nullptr, 0, d, st, split_units_digits(d.R, d.KC),
                    CoefArgs{}, stream);
     DMP_CHECK_HIP(hipGetLastError());
     return DMP_OK;
@@ -407,13 +458,13 @@ int launch_split_grouped_rowmax(const SplitDesc* descs_dev, int count, int units
 
 int launch_split_grouped_digits(const SplitDesc* descs_dev, int count, int units, int S,
                                 dmp_kind kind, const DevState* st, hipStream_t stream,
-                                const CoefArgs& coef) {
+                                const CoefArgs& coef, bool combined) {
     if (units + coef.count <= 0) return DMP_OK;
     if (kind == DMP_MARKIDIS_FP16)
-        k_digits<2, true, true><<<units + coef.count, 256, 0, stream>>>(descs_dev, count,
-                                                                       SplitDesc{}, st, coef);
+        launch_halves(combined, descs_dev, count, SplitDesc{}, st, units, coef, stream);
     else
-        kDigits[S](kind == DMP_OZ_FP16, descs_dev, count, SplitDesc{}, st, units, coef, stream);
+        kDigits[S](kind == DMP_OZ_FP16, combined, descs_dev, count, SplitDesc{}, st, units, coef,
+                   stream);
     DMP_CHECK_HIP(hipGetLastError());
     return DMP_OK;
 }
