@@ -649,6 +649,7 @@ int dmp_purify_bwd(const dmp_tape* t, const double* Pbar, double* Hbar, void* ws
         set_error("workspace of %zu bytes required", need);
         return DMP_ENOMEM;
     }
+    DMP_CHECK(check_workspace_alignment(ws));
     const int n = t->n;
     // one purification at a time per process (see purify_mutex)
     std::lock_guard<std::mutex> serial(purify_mutex());

@@ -23,20 +23,40 @@ __device__ inline double block_sum(double v, double* sh) {
     return r;
 }
 
-// Fixed-order sum of a matrix's partials, column q.
-__device__ inline double sum_partials(const PurDesc& d, int q, double* sh) {
-    double v = 0.0;
-    for (int i = d.part_begin + threadIdx.x; i < d.part_end; i += 256)
-        v += d.partials[int64_t(i) * kPartials + q];
-    return block_sum(v, sh);
+// Fixed-order sums of a matrix's partials, columns 0 and 1: thread t adds
+// the tiles t, t + 256, ... in that order, then the block sum.  Eight tiles'
+// loads are issued before they are added (the same additions, in the same
+// order, as one load at a time, without a memory latency per tile).
+__device__ inline void sum_partials(const PurDesc& d, double* sh, double* s0, double* s1) {
+    static_assert(kPartials == 2, "two partial columns, loaded as one 16-byte pair");
+    double v0 = 0.0, v1 = 0.0;
+    int i = d.part_begin + int(threadIdx.x);
+    for (; i + 7 * 256 < d.part_end; i += 8 * 256) {
+        double2 t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            t[u] = *reinterpret_cast<const double2*>(d.partials + int64_t(i + u * 256) * kPartials);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            v0 += t[u].x;
+            v1 += t[u].y;
+        }
+    }
+    for (; i < d.part_end; i += 256) {
+        const double2 t = *reinterpret_cast<const double2*>(d.partials + int64_t(i) * kPartials);
+        v0 += t.x;
+        v1 += t.y;
+    }
+    *s0 = block_sum(v0, sh);
+    *s1 = block_sum(v1, sh);
 }
 
 // Canonical purification (Sec. 2.3): c = tr(X2 - P^3) / tr(P - X2), clamped
 // to [0, 1], the branch and the update weights.  One block of 256 threads.
 __device__ inline void coef_canonical(const PurDesc& d, DevState& s, double* sh) {
     if (s.done) return;
-    const double t1 = sum_partials(d, 0, sh);
-    const double t2 = sum_partials(d, 1, sh);
+    double t1, t2;
+    sum_partials(d, sh, &t1, &t2);
     if (threadIdx.x == 0) {
         const double raw = t1 == 0.0 ? 0.5 : t2 / t1;
         const double c = fmin(fmax(raw, 0.0), 1.0);
@@ -62,8 +82,8 @@ __device__ inline void coef_canonical(const PurDesc& d, DevState& s, double* sh)
 // exactly 0) and the branch; the update weights select X2 T, 2X - X2 or X2.
 __device__ inline void coef_trs4(const PurDesc& d, DevState& s, double* sh) {
     if (s.done) return;
-    const double trf = sum_partials(d, 0, sh);
-    const double trg = sum_partials(d, 1, sh);
+    double trf, trg;
+    sum_partials(d, sh, &trf, &trg);
     if (threadIdx.x == 0) {
         const double g = trg == 0.0 ? 0.0 : (double(s.nocc) - trf) / trg;
         s.t1 = trg;

@@ -126,6 +126,7 @@ int dmp_ozaki_gemm(char transA, char transB, int m, int n, int k, const double* 
         set_error("workspace of %zu bytes required", need);
         return DMP_ENOMEM;
     }
+    DMP_CHECK(check_workspace_alignment(ws));
     Carver c(ws);
     GemmLayout g = carve_gemm(c, m, n, k, slices, kind, true);
     const int KC = int(chunks_of(k, kind));
@@ -233,6 +234,7 @@ int dmp_ozaki_gemm_batched(int count, const int* m, const int* n, const int* k,
         set_error("workspace of %zu bytes required", need);
         return DMP_ENOMEM;
     }
+    DMP_CHECK(check_workspace_alignment(ws));
     Carver c(ws);
     std::vector<GemmLayout> lay(count);
     for (int b = 0; b < count; ++b) lay[b] = carve_gemm(c, m[b], n[b], k[b], slices, kind);

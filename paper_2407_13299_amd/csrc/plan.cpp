@@ -45,6 +45,14 @@ int check_kind_slices(dmp_kind kind, int slices) {
     return DMP_OK;
 }
 
+int check_workspace_alignment(const void* ws) {
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) {
+        set_error("workspace %p is not 256-byte aligned", ws);
+        return DMP_EINVAL;
+    }
+    return DMP_OK;
+}
+
 int check_method_flags(int method, int flags) {
     if (method != DMP_CANONICAL && method != DMP_TRS4) {
         set_error("unknown method %d", method);

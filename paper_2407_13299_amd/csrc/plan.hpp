@@ -43,6 +43,9 @@ int check_kind_slices(dmp_kind kind, int slices);
 int validate_purify_args(const double* H, int n, int nocc, double tol, int max_iter,
                          const double* P);
 int check_method_flags(int method, int flags);
+// The caller's workspace starts on a 256-byte boundary (the carved regions
+// are 256-byte aligned relative to it, and kernels load 16-byte vectors).
+int check_workspace_alignment(const void* ws);
 
 // ---- tile orders ----------------------------------------------------------
 // Order of the TM x 64 output tiles of one matrix (TM = 128, or 64 for the

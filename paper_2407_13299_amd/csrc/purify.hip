@@ -250,8 +250,8 @@ __global__ __launch_bounds__(256) void k_finalize_iter(const PurDesc* pd, DevSta
     const PurDesc& d = pd[blockIdx.x];
     DevState& s = states[blockIdx.x];
     if (s.done) return;
-    const double e = sum_partials(d, 0, sh);
-    const double tr = sum_partials(d, 1, sh);
+    double e, tr;
+    sum_partials(d, sh, &e, &tr);
     if (threadIdx.x == 0) {
         const double de = e - s.E;
         s.dE_prev = s.dE;
@@ -940,6 +940,7 @@ int purify_many(int count, const double* const* H, const int* n, const int* nocc
         set_error("workspace of %zu bytes required", c.used());
         return DMP_ENOMEM;
     }
+    DMP_CHECK(check_workspace_alignment(ws));
     // one purification at a time per process (see purify_mutex)
     std::lock_guard<std::mutex> serial(purify_mutex());
     std::vector<std::unique_ptr<GroupHost>> keep;

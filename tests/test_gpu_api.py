@@ -48,6 +48,36 @@ def test_purify_uses_a_caller_workspace():
     assert torch.equal(p0, p1) and e0 == e1
 
 
+def test_misaligned_workspace_is_rejected():
+    """A workspace that does not start on a 256-byte boundary is an argument
+    error (DMP_EINVAL) at the C ABI, before any work is queued."""
+    import ctypes
+    from paper_2407_13299_amd import _lib
+    lib = _lib.load()
+    a = dev(np.ones((70, 50)))
+    b = dev(np.ones((50, 40)))
+    c = torch.full((70, 40), 7.0, dtype=torch.float64, device="cuda")
+    need = lib.dmp_gemm_workspace_bytes(70, 40, 50, 3, _lib.KINDS["int8"])
+    ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+    st = lib.dmp_ozaki_gemm(b"N", b"N", 70, 40, 50, a.data_ptr(), 50, b.data_ptr(), 40,
+                            c.data_ptr(), 40, 3, _lib.KINDS["int8"], ws.data_ptr() + 8,
+                            need + 248, None)
+    assert st == -1 and b"aligned" in lib.dmp_last_error()
+    h = dev(np.diag(np.arange(64.0)))
+    p = torch.empty_like(h)
+    e = ctypes.c_double(0.0)
+    need = lib.dmp_purify_workspace_bytes(64, 7, _lib.KINDS["int8"])
+    ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+    st = lib.dmp_purify(h.data_ptr(), 64, 16, 1e-8, 7, _lib.KINDS["int8"], 50, p.data_ptr(),
+                        ctypes.byref(e), None, ws.data_ptr() + 16, need + 240, None)
+    assert st == -1 and b"aligned" in lib.dmp_last_error()
+    torch.cuda.synchronize()
+    assert torch.all(c == 7.0)     # nothing was written
+    st = lib.dmp_purify(h.data_ptr(), 64, 16, 1e-8, 7, _lib.KINDS["int8"], 50, p.data_ptr(),
+                        ctypes.byref(e), None, ws.data_ptr(), need + 256, None)
+    assert st == 0
+
+
 @pytest.mark.parametrize("batched", [False, True])
 def test_gemm_on_a_side_stream(batched):
     """The product is queued on a non-current stream and its temporary
