@@ -315,16 +315,17 @@ __global__ __launch_bounds__(256) void k_digits(const SplitDesc* descs, int coun
     // 2 q + 1 for FP16), so only the packed words stay live, not all digits
     // of the lane's elements.
     uint32_t w[S][4];
-    if constexpr (!FP16 && S <= 8) {
-        // INT8 digits from their integer definition: X = rint(a 2^(8S - 2 - e))
+    if constexpr (S <= 8) {
+        // Digits from their integer definition: X = rint(a 2^(8S - 2 - e))
         // (ties to even; |X| <= 2^(8S - 2) <= 2^62) is the sum of d_s
         // 2^(8 (S - s)) with d_2 .. d_S in [-128, 127], the same digits the
         // rounding steps above give (their sum is rint of the same value, and
         // this balanced representation is unique).  Adding 128 in each of the
         // S - 1 low bytes makes byte S - s of X + bias equal to d_s + 128
         // (s >= 2) and the bytes above it d_1; the digit is that byte with
-        // its top bit flipped.  Exact: the scaling is a power of two, the
-        // halves of X below are exact in FP64.
+        // its top bit flipped (FP16: that signed byte as an FP16 value, exact).
+        // Exact: the scaling is a power of two, the halves of X below are
+        // exact in FP64.
         constexpr uint64_t kBias = S >= 2 ? 0x8080808080808080ull >> (8 * (9 - S)) : 0ull;
 #pragma unroll
         for (int i = 0; i < NE; ++i) {
@@ -335,8 +336,14 @@ __global__ __launch_bounds__(256) void k_digits(const SplitDesc* descs, int coun
 #pragma unroll
             for (int p = 0; p < S; ++p) {
                 const uint32_t byte = (uint32_t(u >> (8 * (S - 1 - p))) & 0xffu) ^ (p > 0 ? 0x80u : 0u);
-                const uint32_t part = byte << (8 * (i & 3));
-                w[p][i >> 2] = (i & 3) == 0 ? part : (w[p][i >> 2] | part);
+                if constexpr (!FP16) {
+                    const uint32_t part = byte << (8 * (i & 3));
+                    w[p][i >> 2] = (i & 3) == 0 ? part : (w[p][i >> 2] | part);
+                } else {
+                    const int digit = int(int8_t(uint8_t(byte)));
+                    const uint32_t part = uint32_t(__half_as_ushort(__int2half_rn(digit))) << (16 * (i & 1));
+                    w[p][i >> 1] = (i & 1) == 0 ? part : (w[p][i >> 1] | part);
+                }
             }
         }
 #pragma unroll
