@@ -8,9 +8,11 @@
 // final carry pass turns a digit of +128 into -128 plus one unit in the
 // digit above, so digits 2..S are signed bytes and digit 1 lies in [-64, 65].
 // Every step is exact in FP64; the value kept is a 2^-e_r rounded to the
-// nearest multiple of 2^-(8S - 2).
+// nearest multiple of 2^-(8S - 2).  Up to S = 8 the kernel forms the same
+// digits from that integer, X = rint(a 2^(8S - 2 - e_r)), and its bytes (see
+// k_digits); the rounding steps above serve S >= 9.
 //
-// Output layout: see common.hpp (fragment blocks of 1 KiB, S planes of one
+// Output layout: see layout.hpp (fragment blocks of 1 KiB, S planes of one
 // (32-row block, chunk) adjacent).
 #include "coef.hpp"
 #include "common.hpp"
