@@ -37,6 +37,39 @@ def test_bitwise_against_oracle_model(kind, s, shape):
 
 
 @pytest.mark.parametrize("kind", ["int8", "fp16"])
+@pytest.mark.parametrize("s", [1, 2, 4, 7, 8, 9])
+def test_ties_and_carries_of_the_split(kind, s):
+    """Entries exactly halfway between two multiples of the last digit's
+    unit (ties, rounded to even), entries whose lower digits round up to 128
+    (carries into the digit above) and entries at the top of the range,
+    multiplied by the identity: the product is the kept value of every entry,
+    bit for bit as the oracle's digits give it, for the digit kernel's
+    integer form (S <= 8) and its rounding steps (S >= 9)."""
+    rng = np.random.default_rng(40 + s)
+    m, k = 96, 160
+    top = 0.75 * np.exp2(rng.integers(-20, 20, (m, 1)))      # row maxima, e = top's exponent + 1
+    _, e = np.frexp(top)
+    unit = np.ldexp(1.0, e - (8 * s - 2))                    # weight of the last digit
+    lim = 2.0 ** (8 * s - 2) * 0.74                          # |X| below the row maximum's
+    ties = (rng.integers(-2 ** 40, 2 ** 40, (m, k)) % int(min(lim, 2 ** 52)) + 0.5) * unit
+    ties *= rng.choice([-1.0, 1.0], (m, k))
+    carry = np.zeros((m, k))
+    if s >= 2:                                               # lower digits 127.5: carries
+        x = sum(127.5 * 256.0 ** i for i in range(s - 1))
+        carry = np.where(rng.random((m, k)) < 0.5, x, -x) * unit
+    pick = rng.integers(0, 3, (m, k))
+    a = np.where(pick == 0, ties, np.where(pick == 1, carry, rng.uniform(-1, 1, (m, k)) * top))
+    a[:, 0] = top[:, 0]
+    a[5, :] = 0.0
+    ident = np.eye(k)
+    got = run(a, ident, s, kind)
+    want = ozaki.ozaki_gemm(a, ident, s)
+    assert np.array_equal(got, want)
+    # the kept value is a rounded to the nearest multiple of the unit, ties to even
+    assert np.array_equal(got, np.rint(a / unit) * unit)
+
+
+@pytest.mark.parametrize("kind", ["int8", "fp16"])
 @pytest.mark.parametrize("s", [9, 10, 12])
 def test_bitwise_many_slices(kind, s):
     rng = np.random.default_rng(s)
