@@ -103,18 +103,20 @@ TILE_CASES = (("int8", 6), ("int8", 7), ("int8", 8), ("fp16", 7))
 TILE_ITERS = 10        # iterations per timed run (stopped by max_iter)
 TILE_MARGIN = 0.015    # a non-default choice must be this much faster
 KIND_IDS = {"int8": 1, "fp16": 2}
-# slice range each measured (kind, S) stands for in the table
-S_RANGES = {("int8", 6): (1, 6), ("int8", 7): (7, 7), ("int8", 8): (8, 12),
-            ("fp16", 7): (1, 7)}
+MAX_SLICES_64 = 8      # largest S with 64-row tiles (kMaxSlices64 in layout.hpp)
+# slice range each measured (kind, S) stands for in the table (S = 9..12 have
+# 128-row tiles only, the table's fallback)
+S_RANGES = {("int8", 6): (1, 6), ("int8", 7): (7, 7), ("int8", 8): (8, 8),
+            ("fp16", 7): (1, 8)}
 
 
 def tile_choices(s):
-    """(rb, split_tail) pairs that exist for S slices (64-row tiles up to S = 7)."""
-    return [(2, 1), (2, 0), (4, 1), (4, 0)] if s <= 7 else [(4, 1), (4, 0)]
+    """(rb, split_tail) pairs that exist for S slices."""
+    return [(2, 1), (2, 0), (4, 1), (4, 0)] if s <= MAX_SLICES_64 else [(4, 1), (4, 0)]
 
 
 def default_choice(s):
-    return (2, 1) if s <= 7 else (4, 1)
+    return (2, 1) if s <= MAX_SLICES_64 else (4, 1)
 
 
 def measure_tiles(sizes=TILE_SIZES, cases=TILE_CASES, rounds=3, seed=11, log=print):

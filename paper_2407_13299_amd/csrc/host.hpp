@@ -44,7 +44,7 @@ struct GemmParams;
 int tile_blocks_for(dmp_kind kind, int S, int n);
 
 // rb: 32-row blocks per tile of the left operand (4, or 2 for the 64-row
-// variant: Ozaki kinds, S <= 7)
+// variant: Ozaki kinds, S <= kMaxSlices64)
 int launch_ozgemm(int S, dmp_kind kind, const GemmParams& p, int ntiles, hipStream_t stream,
                   int rb = 4);
 // Workgroups of the purification-mode slice GEMM (kind, S, rb) resident on

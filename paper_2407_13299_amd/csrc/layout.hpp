@@ -38,6 +38,9 @@ constexpr int kGemmThreads = 512;    // 8 wavefronts, one 32 x 32 quadrant each
 constexpr int kPad = 128;            // row padding of the digit planes
 constexpr int kKPad = 64;            // reduction padding of the digit planes
 constexpr int kMaxSlices = 12;
+// Largest S with 64-row purification tiles (two workgroups per CU fit the
+// registers without spills up to here).
+constexpr int kMaxSlices64 = 8;
 constexpr int kTopBits = 6;          // fractional bits of the first digit
 constexpr int kDigitBits = 8;        // bits of every further digit
 // Exponent recorded for a row (column) holding a NaN or an infinity; the

@@ -575,7 +575,7 @@ static bool purification_mode(int mode) {
 template <int S, int PHASE>
 static void launch_s(bool fp16, const GemmParams& p, int ntiles, int rb, hipStream_t stream) {
     const bool pur = PHASE == kPiece || purification_mode(p.mode);
-    if constexpr (S <= 7) {   // the 64-row variant exists up to S = 7
+    if constexpr (S <= kMaxSlices64) {   // the 64-row variant
         if (rb == 2) {
             if (fp16 && pur)
                 k_ozgemm<S, true, 0, true, 2, PHASE><<<ntiles, 256, 0, stream>>>(p);
@@ -606,7 +606,7 @@ static void launch_s(bool fp16, const GemmParams& p, int ntiles, int rb, hipStre
 template <int S>
 static int resident_s(bool fp16, int rb, int* per_cu) {
     hipError_t e;
-    if constexpr (S <= 7) {
+    if constexpr (S <= kMaxSlices64) {
         if (rb == 2) {
             e = fp16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_ozgemm<S, true, 0, true, 2>, 256, 0)
                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_ozgemm<S, false, 0, true, 2>, 256, 0);
@@ -648,8 +648,8 @@ static const TermsFn kTerms[kMaxTerms + 1] = {nullptr, launch_terms<1>, launch_t
 int launch_ozgemm(int S, dmp_kind kind, const GemmParams& p, int ntiles, hipStream_t stream,
                   int rb) {
     if (ntiles <= 0) return DMP_OK;
-    if (rb != 4 && (rb != 2 || kind == DMP_MARKIDIS_FP16 || S > 7)) {
-        set_error("64-row tiles exist for the Ozaki kinds with S <= 7 only");
+    if (rb != 4 && (rb != 2 || kind == DMP_MARKIDIS_FP16 || S > kMaxSlices64)) {
+        set_error("64-row tiles exist for the Ozaki kinds with S <= %d only", kMaxSlices64);
         return DMP_EINVAL;
     }
     if (p.fix != nullptr) {
@@ -679,7 +679,7 @@ int launch_ozgemm(int S, dmp_kind kind, const GemmParams& p, int ntiles, hipStre
 int gemm_slots(int S, dmp_kind kind, int rb, int* slots) {
     *slots = 0;
     if ((kind != DMP_OZ_INT8 && kind != DMP_OZ_FP16) || S < 1 || S > kMaxSlices ||
-        (rb == 2 && S > 7) || (rb != 2 && rb != 4)) {
+        (rb == 2 && S > kMaxSlices64) || (rb != 2 && rb != 4)) {
         set_error("no slice GEMM for this kind, S and tile height");
         return DMP_EINVAL;
     }

@@ -186,9 +186,9 @@ void batch_slices(int count, const int* n, int slices, dmp_kind kind, std::vecto
 }
 
 TileChoice tile_choice(dmp_kind kind, int S, int n, int forced_rb) {
-    // 64-row tiles exist for the Ozaki kinds up to S = 7 (beyond that two
-    // workgroups no longer fit a CU without spills)
-    const bool has64 = (kind == DMP_OZ_INT8 || kind == DMP_OZ_FP16) && S >= 1 && S <= 7;
+    // 64-row tiles exist for the Ozaki kinds up to kMaxSlices64 (beyond that
+    // two workgroups no longer fit a CU without spills)
+    const bool has64 = (kind == DMP_OZ_INT8 || kind == DMP_OZ_FP16) && S >= 1 && S <= kMaxSlices64;
     TileChoice c{4, true};
     for (const TileRule& r : kTileTable) {
         if (r.kind == int(kind) && S >= r.s_lo && S <= r.s_hi && n >= r.n_lo && n <= r.n_hi) {

@@ -44,9 +44,9 @@ def _tile_choice_exe(tmp_path):
     return exe
 
 
-def _tile_choice(exe, queries):
+def _tile_choice(exe, queries, forced=0):
     import subprocess
-    text = "".join(f"{k} {s} {n}\n" for k, s, n in queries)
+    text = "".join(f"{k} {s} {n} {forced}\n" for k, s, n in queries)
     out = subprocess.run([exe], input=text, capture_output=True, text=True, check=True).stdout
     return [tuple(int(x) for x in line.split()) for line in out.splitlines()]
 
@@ -55,7 +55,7 @@ def test_tile_table_picks_the_measured_winners(tmp_path):
     """tuned_tiles.h as compiled into the library: for every size it was
     measured at, tile_choice returns the winner recorded beside the
     measurement; rows of one (kind, slice range) cover every size once;
-    64-row tiles only up to S = 7."""
+    64-row tiles only up to S = 8."""
     import os
     hdr = os.path.join(os.path.dirname(autotune.__file__), "csrc", "tuned_tiles.h")
     text = open(hdr).read()
@@ -65,7 +65,7 @@ def test_tile_table_picks_the_measured_winners(tmp_path):
     assert rules
     for k, s_lo, s_hi, n_lo, n_hi, rb, split in rules:
         assert rb in (2, 4) and split in (0, 1) and n_lo <= n_hi and s_lo <= s_hi
-        assert rb == 4 or s_hi <= 7
+        assert rb == 4 or s_hi <= autotune.MAX_SLICES_64
     for key in {(r[0], r[1], r[2]) for r in rules}:
         spans = sorted((r[3], r[4]) for r in rules if (r[0], r[1], r[2]) == key)
         assert spans[0][0] == 1 and spans[-1][1] == 1 << 30
@@ -77,8 +77,11 @@ def test_tile_table_picks_the_measured_winners(tmp_path):
         got = _tile_choice(exe, q)
         want = [(int(rows) // 32, 1 if sp == "split" else 0) for _, _, _, rows, sp in measured]
         assert got == want
-    # 64-row tiles never beyond S = 7, whatever the table says
-    assert all(rb == 4 for rb, _ in _tile_choice(exe, [(1, 8, 512), (1, 12, 8192), (2, 9, 100)]))
+    # 64-row tiles never beyond S = 8, whatever the table or the forced height says
+    assert all(rb == 4 for rb, _ in _tile_choice(exe, [(1, 9, 512), (1, 12, 8192), (2, 9, 100)]))
+    assert all(rb == 4 for rb, _ in _tile_choice(exe, [(1, 9, 512), (2, 12, 100)], forced=2))
+    # the Markidis kind has no 64-row tiles
+    assert all(rb == 4 for rb, _ in _tile_choice(exe, [(3, 2, 512)], forced=2))
 
 
 def test_tile_ranges_merge_and_cover():

@@ -303,8 +303,8 @@ def test_side_stream_and_concurrent_threads():
 
 @pytest.mark.parametrize("method", ["canonical", "trs4"])
 def test_both_tile_heights_match_the_oracle(method, monkeypatch):
-    """The purification products run on 64-row tiles for S <= 7 and on 128-row
-    tiles otherwise; DMP_TILE_ROWS=128 forces the 128-row kernel.  Both reach
+    """The purification products run on 64-row or 128-row tiles, as the tuned
+    table says; DMP_TILE_ROWS=64 / 128 forces one of them.  Both reach
     the projector; they differ only in the fixed order of the trace sums."""
     h, _, _ = spectrum_hamiltonian(300, 150, seed=9)
     p_ref, e_ref, _, _ = projector.eigh_projector(h, 150)
