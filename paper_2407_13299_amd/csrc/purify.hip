@@ -608,6 +608,8 @@ int launch_oz_iteration(GroupPlan& g, int par, hipStream_t s,
     return DMP_OK;
 }
 
+// Iterations per replay of the cached graph: even, so a replay ends with the
+// iterate in the buffer it started from.
 int iterations_per_sync(int max_n) {
     if (max_n >= 4096) return 2;
     if (max_n >= 1024) return 4;
@@ -721,10 +723,12 @@ int run_oz_timed(std::vector<GroupPlan>& groups, int max_iter, int m, hipStream_
 
 // Run the Ozaki groups to completion.  Iterations run in replays of m at a
 // time (one cached graph, or eager launches with DMP_NO_GRAPH=1); matrices
-// that have stopped skip their work inside every launch.  The host reads the
-// device states once after the number of replays the previous run of the
-// same launch sequence needed (a first run: after one replay); a run that
-// needs more continues with one replay always queued ahead of the state read
+// that have stopped skip their work inside every launch.  Once a run of the
+// same launch sequence has finished, later runs start with one launch of a
+// second cached graph holding as many iterations as that run needed
+// (rounded up to a multiple of m), and the host reads the device states
+// once after it; a first run reads them after one replay.  A run that needs
+// more continues with replays of m, one always queued ahead of the state read
 // being checked, so the GPU does not wait for the host between replays.
 int run_oz_groups(std::vector<GroupPlan>& groups, int max_iter, hipStream_t s,
                   std::vector<DevState>& host_st, const int* n) {
@@ -785,6 +789,21 @@ int run_oz_groups(std::vector<GroupPlan>& groups, int max_iter, hipStream_t s,
                           ? std::min(max_replays, std::max(1, (cg->last_iters + m - 1) / m))
                           : 1;
     int launched = 0;
+    // the predicted iterations as one graph (same parity at its end as after
+    // ``first`` replays of m, since m is even)
+    std::shared_ptr<CachedGraph> whole;
+    if (cg && first > 1) {
+        int dev = 0;
+        DMP_CHECK_HIP(hipGetDevice(&dev));
+        const int env = (tail_split_enabled() ? 1 : 0) | 2;
+        whole = graph_cache().get_or_create(launch_key(groups, first * m, dev, env), [&]() {
+            return capture_iterations(groups, first * m);
+        });
+    }
+    if (whole) {
+        DMP_CHECK_HIP(hipGraphLaunch(whole->exec, s));
+        launched = first;
+    }
     for (; launched < first; ++launched) DMP_CHECK(replay());
     DMP_CHECK(read(0));
     DMP_CHECK_HIP(hipEventSynchronize(ev[0]));
