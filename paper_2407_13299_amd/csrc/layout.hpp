@@ -140,7 +140,9 @@ struct SplitDesc {
     int ub_rowmax;      // first k_rowmax unit of this matrix (grouped)
     int ub_digits;      // first k_digits unit of this matrix (grouped)
     int state_index;    // -1: no state
-    int pad_;
+    int sym;            // 1: A is symmetric and only its upper triangle (k >= r)
+                        // holds it (trans == 0, A2 null): entry (r, k < r) is
+                        // read as A[k, r]
 };
 
 // Per-matrix arguments of the small purification kernels.
@@ -208,6 +210,9 @@ struct GemmParams {
     // sums: exact in any order) and runs the epilogue.
     int* fix;
     int nfull, nsplit;
+    // purification modes: 1 stores only the upper triangle of the output
+    // (no mirror; the next splits read it as symmetric, SplitDesc::sym)
+    int upper_only;
 };
 
 // Tail split of a slice-GEMM launch: at most kMaxSplit parts per tile, at

@@ -33,6 +33,8 @@
 //   EPI_UPDATE  P' = alpha P + beta X2 + gamma (X2 P) for row <= col,
 //               mirrored; tile partials of tr(P' H) and tr P' (gamma == 0:
 //               no products at all, P' = alpha P + beta X2)
+// (GemmParams::upper_only: the purification modes store the upper triangle
+// only; the row maxima still cover the mirror's rows)
 //   EPI_SQUARE_TRS4  X2 = X X as EPI_SQUARE; partials of tr F = tr(X2 (4X -
 //               3 X2)) and tr G = ||X - X2||_F^2 (TRS4, Sec. 3)
 // In the purification modes only the upper triangle is computed and kept,
@@ -501,7 +503,7 @@ __global__ __launch_bounds__(128 * RB, RB == 4 ? 1 : 2) void k_ozgemm(GemmParams
                 if (diag) s1 += w;
             }
             d.out[ij] = w;
-            if (!diag) d.out[ji] = w;
+            if (!diag && !p.upper_only) d.out[ji] = w;
             bits = absbits(w);
             cmax = bits > cmax ? bits : cmax;      // its mirror (col, row) of row ``col``
         }

@@ -378,14 +378,20 @@ void build_group(GroupPlan& g, const double* const* H, double* const* P, const i
         // Row maxima: those of P come from the update's epilogue (of P0 from
         // k_rowmax), those of X2 from the square's; each array is zeroed by
         // the split that runs just before its producer.
+        // canonical purification keeps its iterates and X2 as upper triangles
+        // (upper_only products), so their splits read them as symmetric;
+        // TRS4's combined operand needs full rows of both
+        const int sym = g.method == DMP_CANONICAL ? 1 : 0;
         sd.A = P[m];
         sd.maxbits = L.maxP;
         sd.expo = L.expP;
         sd.planes = L.planesP;
         sd.clear = L.maxX;
+        sd.sym = sym;
         out.sp0[b] = sd;
         sd.A = L.Pw;
         out.sp1[b] = sd;
+        sd.sym = 0;
         // TRS4: T = ta P + tb X2 + tc I, split into P's planes (free once the
         // square has run); its row maxima (k_rowmax) go to X2's array, free
         // once X2 is split
@@ -402,6 +408,7 @@ void build_group(GroupPlan& g, const double* const* H, double* const* P, const i
         sd.expo = L.expX;
         sd.planes = L.planesX;
         sd.clear = L.maxP;
+        sd.sym = sym;
         out.sx[b] = sd;
         MatDesc md{};
         md.a_rb_stride = rbs;

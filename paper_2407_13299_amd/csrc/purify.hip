@@ -165,6 +165,16 @@ __global__ __launch_bounds__(256) void k_finalize_init(const PurDesc* pd, DevSta
     }
 }
 
+// Tile pair (I, J), I <= J, number pi of the T x T tile triangle numbered
+// row by row (row I holds pairs [I T - I (I - 1) / 2, ...)).
+__device__ inline int2 tile_pair(int pi, int T) {
+    int I = int((2.0 * T + 1.0 - sqrt((2.0 * T + 1.0) * (2.0 * T + 1.0) - 8.0 * pi)) * 0.5);
+    auto first = [&](int r) { return r * T - r * (r - 1) / 2; };
+    if (I > 0 && first(I) > pi) --I;
+    if (I + 1 < T && first(I + 1) <= pi) ++I;
+    return make_int2(I, I + (pi - first(I)));
+}
+
 // P0 = lam (mu I - H) + theta I from the upper triangle of H (mirrored), and
 // partial energies tr(P0 H); fixed grid of kE0Blocks blocks per matrix.
 // Block x takes the 32 x 32 tile pairs (I, J), I <= J, numbered row by row,
@@ -189,12 +199,8 @@ __global__ __launch_bounds__(256) void k_init_p0(const PurDesc* pd, const DevSta
     double e = 0.0;
     if (!s.nonfinite) {
         for (int pi = blockIdx.x; pi < npairs; pi += kE0Blocks) {
-            // row I of the pair triangle holds pairs [I T - I (I - 1) / 2, ...)
-            int I = int((2.0 * T + 1.0 - sqrt((2.0 * T + 1.0) * (2.0 * T + 1.0) - 8.0 * pi)) * 0.5);
-            auto first = [&](int r) { return r * T - r * (r - 1) / 2; };
-            if (I > 0 && first(I) > pi) --I;
-            if (I + 1 < T && first(I + 1) <= pi) ++I;
-            const int J = I + (pi - first(I));
+            const int2 ij = tile_pair(pi, T);
+            const int I = ij.x, J = ij.y;
             for (int r = ty; r < 32; r += 8) {
                 const int i = I * 32 + r, j = J * 32 + tx;
                 double p = 0.0;
@@ -218,6 +224,36 @@ __global__ __launch_bounds__(256) void k_init_p0(const PurDesc* pd, const DevSta
     }
     e = block_sum(e, sh);
     if (threadIdx.x == 0) d.e0[blockIdx.x] = e;
+}
+
+// The final iterate of a canonical Ozaki purification, which the products
+// keep as its upper triangle, made full in place: tile (J, I) from tile
+// (I, J), transposed through LDS, both with coalesced rows.  Grid
+// (kE0Blocks, matrices); matrices that ran no iteration hold the full P0.
+__global__ __launch_bounds__(256) void k_mirror_iterate(const PurDesc* pd, const DevState* states) {
+    __shared__ double t[32][33];
+    const PurDesc& d = pd[blockIdx.y];
+    const DevState& s = states[blockIdx.y];
+    if (s.iters == 0) return;
+    const int n = d.n;
+    double* X = d.Pb[s.iters & 1];
+    const int T = (n + 31) / 32;
+    const int npairs = T * (T + 1) / 2;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int pi = blockIdx.x; pi < npairs; pi += kE0Blocks) {
+        const int2 ij = tile_pair(pi, T);
+        const int I = ij.x, J = ij.y;
+        for (int r = ty; r < 32; r += 8) {
+            const int i = I * 32 + r, j = J * 32 + tx;
+            t[r][tx] = (i < n && j < n) ? X[int64_t(i) * n + j] : 0.0;
+        }
+        __syncthreads();
+        for (int r = ty; r < 32; r += 8) {
+            const int i = J * 32 + r, j = I * 32 + tx;   // (i, j) = (j, i) of the upper part
+            if (i < n && j < n && (I != J || j < i)) X[int64_t(i) * n + j] = t[tx][r];
+        }
+        __syncthreads();
+    }
 }
 
 __global__ __launch_bounds__(256) void k_finalize_e0(const PurDesc* pd, DevState* states) {
@@ -583,6 +619,9 @@ int launch_oz_iteration(GroupPlan& g, int par, hipStream_t s,
     p.states = g.st;
     const bool trs4 = g.method == DMP_TRS4;
     p.mode = trs4 ? EPI_SQUARE_TRS4 : EPI_SQUARE;
+    // canonical iterates and X2 stay upper triangles (their splits read them
+    // as symmetric); TRS4's combined operand needs full rows
+    p.upper_only = trs4 ? 0 : 1;
     p.spread = g.count > 1 ? 1 : 0;
     if (g.tail.nsplit > 1) {
         p.fix = g.fix;
@@ -992,6 +1031,11 @@ int purify_many(int count, const double* const* H, const int* n, const int* nocc
         }
     } else {
         DMP_CHECK(run_oz_groups(groups, max_iter, s, host_st, n));
+        for (auto& g : groups)
+            if (g.method == DMP_CANONICAL) {
+                k_mirror_iterate<<<dim3(kE0Blocks, g.count), 256, 0, s>>>(g.pd, g.st);
+                DMP_CHECK_HIP(hipGetLastError());
+            }
     }
     if (flags & DMP_REFINE_MCWEENY) {
         size_t off = 0;

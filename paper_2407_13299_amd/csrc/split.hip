@@ -186,9 +186,13 @@ __device__ inline int exponent_of(uint64_t bits) {
 // Operand rows that are matrix rows (trans == 0, also the combined operand)
 // are first staged through LDS: the workgroup reads the 32 x W panel row by
 // row, each wave 64 consecutive doubles per load, so the HBM reads are
-// coalesced although every lane then needs a piece of its own row.  Columns
-// (trans == 1) are read directly: there consecutive lanes own consecutive
-// rows, which are adjacent in memory.
+// coalesced although every lane then needs a piece of its own row.  A
+// symmetric source kept as its upper triangle (d.sym) is read the same way
+// where the panel lies above the diagonal, as the transposed panel (32
+// contiguous doubles of each of W rows) where it lies below, and entry by
+// entry where it crosses the diagonal.  Columns (trans == 1) are read
+// directly: there consecutive lanes own consecutive rows, which are adjacent
+// in memory.
 // HALVES (Markidis kind, S = 2, FP16): instead of digits, the high and low
 // FP16 parts of x = a 2^-e (|x| < 1): X0 = FP16[x], X1 = FP16[x - X0].
 // COMB: the operand is the combination ta A + tb A2 + tc I (d.A2 set; the
@@ -239,6 +243,7 @@ __global__ __launch_bounds__(256) void k_digits(const SplitDesc* descs, int coun
         // are in flight per lane
         const int kb = kq * W;
         double stage[PER];
+        bool transposed = false;   // stage[t] holds entry (q % 32, q / 32)
         if constexpr (COMB) {
             double stage2[PER];
 #pragma unroll
@@ -259,6 +264,28 @@ __global__ __launch_bounds__(256) void k_digits(const SplitDesc* descs, int coun
                                ? combine(ta, tb, tc, stage[t], stage2[t], row == k)
                                : 0.0;
             }
+        } else if (d.sym && kb + W <= rb * kFragRows) {
+            // symmetric source, panel entirely below the diagonal: entry
+            // (row, k) is A[k, row], so thread q reads row k = kb + q / 32 at
+            // column row = 32 rb + q % 32 (32 contiguous doubles per k)
+            transposed = true;
+#pragma unroll
+            for (int t = 0; t < PER; ++t) {
+                const int q = threadIdx.x + 256 * t, rr = q % kFragRows, cc = q / kFragRows;
+                const int row = rb * kFragRows + rr, k = kb + cc;
+                stage[t] = (row < d.R && k < d.K) ? d.A[int64_t(k) * d.lda + row] : 0.0;
+            }
+        } else if (d.sym && kb < rb * kFragRows + kFragRows - 1) {
+            // symmetric source, panel across the diagonal: every entry from
+            // its place in the upper triangle
+#pragma unroll
+            for (int t = 0; t < PER; ++t) {
+                const int q = threadIdx.x + 256 * t, rr = q / W, cc = q % W;
+                const int row = rb * kFragRows + rr, k = kb + cc;
+                stage[t] = (row < d.R && k < d.K)
+                               ? d.A[k >= row ? int64_t(row) * d.lda + k : int64_t(k) * d.lda + row]
+                               : 0.0;
+            }
         } else {
 #pragma unroll
             for (int t = 0; t < PER; ++t) {
@@ -267,10 +294,18 @@ __global__ __launch_bounds__(256) void k_digits(const SplitDesc* descs, int coun
                 stage[t] = (row < d.R && k < d.K) ? d.A[int64_t(row) * d.lda + k] : 0.0;
             }
         }
+        if (transposed) {
 #pragma unroll
-        for (int t = 0; t < PER; ++t) {
-            const int q = threadIdx.x + 256 * t;
-            panel[(q / W) * LDW + q % W] = stage[t];
+            for (int t = 0; t < PER; ++t) {
+                const int q = threadIdx.x + 256 * t;
+                panel[(q % kFragRows) * LDW + q / kFragRows] = stage[t];
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < PER; ++t) {
+                const int q = threadIdx.x + 256 * t;
+                panel[(q / W) * LDW + q % W] = stage[t];
+            }
         }
         __syncthreads();
         if (kc >= d.KC) return;
