@@ -275,9 +275,12 @@ int dmp_autotune_slices(int n, double target, dmp_kind kind);
  * Adjoint of the purification (reverse mode).  dmp_purify_fwd_tape runs
  * dmp_purify and records, for every iteration, the branch, c and the
  * traces, plus a copy of H and the iterate P_k for every k that is a
- * multiple of ckpt_stride (ckpt_stride <= 0 picks ceil(sqrt(max_iter))),
- * in device memory owned by the tape (allocated here, released by
- * dmp_tape_free).  Only the Ozaki kinds are supported.
+ * multiple of ckpt_stride, in device memory owned by the tape (allocated
+ * here, released by dmp_tape_free).  ckpt_stride = 1 also keeps X2_k = P_k^2
+ * of every step, so that the backward pass recomputes nothing;
+ * ckpt_stride <= 0 picks 1 when 2 max_iter n^2 doubles take at most a
+ * quarter of the free device memory, else ceil(sqrt(max_iter)).  Only the
+ * Ozaki kinds are supported.
  * dmp_purify_bwd takes Pbar = dL/dP (device, symmetric n x n; for
  * L = tr(P W) it is W) and writes Hbar = dL/dH (device, symmetric), the
  * derivative of the recorded iteration (fixed branch pattern) including the
@@ -285,7 +288,8 @@ int dmp_autotune_slices(int n, double target, dmp_kind kind);
  * Gershgorin bounds.  Iterates between checkpoints are recomputed with the
  * same products, so every ckpt_stride gives the same Hbar bit for bit.
  * Each backward step costs 3 products (M = Y P and M P in full, the
- * symmetric P M on its upper triangle) plus the recomputation of 2.
+ * symmetric P M on its upper triangle), plus the recomputation of 2 unless
+ * the tape holds every step (ckpt_stride 1).
  * ------------------------------------------------------------------- */
 typedef struct dmp_tape dmp_tape;
 int dmp_purify_fwd_tape(const double* H, int n, int nocc, double tol,

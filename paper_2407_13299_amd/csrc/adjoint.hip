@@ -416,6 +416,8 @@ struct dmp_tape {
     std::vector<double> c, t1, t2;
     std::vector<int> branch, clamped;
     std::vector<double*> ckpt;   // device copies of P_0, P_stride, ...
+    std::vector<double*> x2;     // stride 1: X2_0, X2_1, ... as well (no recomputation)
+    std::vector<void*> owned;    // the device allocations holding them
     void* fwd_ws = nullptr;      // forward workspace (owned)
     double* H_copy = nullptr;    // tape-owned copy of H (the caller's may change)
 };
@@ -427,7 +429,7 @@ void dmp_tape_free(dmp_tape* t) {
     int cur = 0;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(t->device);
-    for (double* p : t->ckpt) (void)hipFree(p);
+    for (void* p : t->owned) (void)hipFree(p);
     if (t->fwd_ws) (void)hipFree(t->fwd_ws);
     if (t->H_copy) (void)hipFree(t->H_copy);
     (void)hipSetDevice(cur);
@@ -485,8 +487,17 @@ int dmp_purify_fwd_tape(const double* H, int n, int nocc, double tol, int slices
         set_error("n = %d exceeds the exact INT32 range for %d slices", n, slices);
         return DMP_EINVAL;
     }
-    const int stride = ckpt_stride > 0 ? ckpt_stride
-                                       : std::max(1, int(std::ceil(std::sqrt(double(max_iter)))));
+    // default: every iterate and its square when the worst case (max_iter
+    // steps) takes at most a quarter of the free device memory (then the
+    // backward recomputes nothing), else checkpoints every sqrt(max_iter)
+    int stride = ckpt_stride;
+    if (stride <= 0) {
+        size_t free_b = 0, total_b = 0;
+        const double full = 2.0 * double(max_iter) * double(n) * double(n) * sizeof(double);
+        const bool fits = hipMemGetInfo(&free_b, &total_b) == hipSuccess && full <= 0.25 * double(free_b);
+        (void)hipGetLastError();
+        stride = fits ? 1 : std::max(1, int(std::ceil(std::sqrt(double(max_iter)))));
+    }
     // one purification at a time per process (see purify_mutex)
     std::lock_guard<std::mutex> serial(purify_mutex());
     dmp_tape* t = new dmp_tape();
@@ -539,15 +550,32 @@ int dmp_purify_fwd_tape(const double* H, int n, int nocc, double tol, int slices
         return st;
     }
     t->init = h;
-    auto checkpoint = [&](const double* src) -> int {
-        double* d = nullptr;
-        if (hipMalloc(&d, size_t(n) * n * sizeof(double)) != hipSuccess) {
-            set_error("hipMalloc of a checkpoint failed");
-            return DMP_ENOMEM;
+    // n x n device slots owned by the tape, allocated in blocks that double
+    // in size (8, 16, ... slots): a few allocations for a whole run
+    const size_t nn = size_t(n) * n;
+    std::vector<double*> pool;
+    size_t grow = 8;
+    auto slot = [&](double** out) -> int {
+        if (pool.empty()) {
+            void* blk = nullptr;
+            if (hipMalloc(&blk, grow * nn * sizeof(double)) != hipSuccess) {
+                (void)hipGetLastError();
+                set_error("hipMalloc of %zu tape slots failed", grow);
+                return DMP_ENOMEM;
+            }
+            t->owned.push_back(blk);
+            for (size_t i = grow; i-- > 0;) pool.push_back(static_cast<double*>(blk) + i * nn);
+            grow = std::min<size_t>(grow * 2, 64);
         }
-        t->ckpt.push_back(d);
-        const hipError_t e = hipMemcpyAsync(d, src, size_t(n) * n * sizeof(double),
-                                            hipMemcpyDefault, s);
+        *out = pool.back();
+        pool.pop_back();
+        return DMP_OK;
+    };
+    auto checkpoint = [&](const double* src, std::vector<double*>& into) -> int {
+        double* d = nullptr;
+        DMP_CHECK(slot(&d));
+        into.push_back(d);
+        const hipError_t e = hipMemcpyAsync(d, src, nn * sizeof(double), hipMemcpyDefault, s);
         if (e != hipSuccess) {
             set_error("checkpoint copy failed: %s", hipGetErrorString(e));
             return DMP_EHIP;
@@ -556,9 +584,18 @@ int dmp_purify_fwd_tape(const double* H, int n, int nocc, double tol, int slices
     };
     double* cur = P;
     double* nxt = Pw;
-    if (!h.done) st = checkpoint(P);
+    if (!h.done) st = checkpoint(P, t->ckpt);
+    if (stride == 1 && !h.done) cur = t->ckpt[0];
     for (int k = 0; st == DMP_OK && !h.done && k < max_iter; ++k) {
-        st = forward_iteration(x, cur, X2, nxt, true, s);
+        // stride 1: X2_k and P_{k+1} are written straight into tape slots
+        double* x2k = X2;
+        if (stride == 1) {
+            st = slot(&x2k);
+            if (st == DMP_OK) st = slot(&nxt);
+            if (st != DMP_OK) break;
+            t->x2.push_back(x2k);
+        }
+        st = forward_iteration(x, cur, x2k, nxt, true, s);
         if (st != DMP_OK) break;
         if (hipMemcpyAsync(&h, x.st, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) {
@@ -571,8 +608,13 @@ int dmp_purify_fwd_tape(const double* H, int n, int nocc, double tol, int slices
         t->t1.push_back(h.t1);
         t->t2.push_back(h.t2);
         t->clamped.push_back(h.clamped);
-        std::swap(cur, nxt);
-        if (!h.done && (k + 1) % stride == 0) st = checkpoint(cur);
+        if (stride == 1) {
+            cur = nxt;
+            if (!h.done) t->ckpt.push_back(cur);
+        } else {
+            std::swap(cur, nxt);
+            if (!h.done && (k + 1) % stride == 0) st = checkpoint(cur, t->ckpt);
+        }
     }
     if (st != DMP_OK) {
         dmp_tape_free(t);
@@ -672,16 +714,21 @@ int dmp_purify_bwd(const dmp_tape* t, const double* Pbar, double* Hbar, void* ws
     fresh.iters = 0;
     const int K = t->K;
     const int nseg = (K + t->stride - 1) / t->stride;
+    // every step's P and X2 on the tape: nothing to recompute
+    const bool stored = t->stride == 1 && int(t->x2.size()) == K && int(t->ckpt.size()) >= K;
     for (int seg = nseg - 1; seg >= 0; --seg) {
         const int start = seg * t->stride, end = std::min(start + t->stride, K);
-        DMP_CHECK_HIP(hipMemcpyAsync(segP[0], t->ckpt[seg], size_t(n) * n * sizeof(double),
-                                     hipMemcpyDeviceToDevice, s));
-        DMP_CHECK_HIP(hipMemcpyAsync(x.st, &fresh, sizeof(fresh), hipMemcpyHostToDevice, s));
-        for (int j = start; j < end; ++j)
-            DMP_CHECK(forward_iteration(x, segP[j - start], segX[j - start], segP[j - start + 1], false, s));
+        if (!stored) {
+            DMP_CHECK_HIP(hipMemcpyAsync(segP[0], t->ckpt[seg], size_t(n) * n * sizeof(double),
+                                         hipMemcpyDeviceToDevice, s));
+            DMP_CHECK_HIP(hipMemcpyAsync(x.st, &fresh, sizeof(fresh), hipMemcpyHostToDevice, s));
+            for (int j = start; j < end; ++j)
+                DMP_CHECK(forward_iteration(x, segP[j - start], segX[j - start], segP[j - start + 1],
+                                            false, s));
+        }
         for (int j = end - 1; j >= start; --j) {
-            const double* P = segP[j - start];
-            const double* X2 = segX[j - start];
+            const double* P = stored ? t->ckpt[j] : segP[j - start];
+            const double* X2 = stored ? t->x2[j] : segX[j - start];
             // M = Y P, MP = M P, PM = P M.  The row and column maxima of M
             // come from its product's epilogue (x.ma, x.mc: zeroed by the
             // digit kernels of the two splits before it, once their own
