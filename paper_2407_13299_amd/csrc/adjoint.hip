@@ -188,6 +188,21 @@ int forward_iteration(const OzCtx& x, const double* P_in, double* X2_out, double
     return DMP_OK;
 }
 
+// Coefficient data of one recorded step.
+struct StepRecord {
+    double c, t1, t2;
+    int branch, clamped;
+};
+
+// Records the step the state has just finished (index iters - 1); once the
+// run has stopped, every later launch rewrites that entry with the same
+// values.
+__global__ void k_record_step(const DevState* st, StepRecord* hist) {
+    const DevState& s = *st;
+    if (threadIdx.x == 0 && s.iters > 0)
+        hist[s.iters - 1] = StepRecord{s.c, s.t1, s.t2, s.branch, s.clamped};
+}
+
 // C = A B for n x n operands already split: (pa, ea) rows of A, (pb, eb)
 // columns of B.  rowmax / colmax (nullable, zeroed beforehand) receive the
 // maxima of |C| per row / column for the splits of C.  ``sym``: C is known
@@ -582,20 +597,50 @@ int dmp_purify_fwd_tape(const double* H, int n, int nocc, double tol, int slices
         }
         return DMP_OK;
     };
+    // the coefficient data of every step, recorded on the device and read
+    // once at the end; the state is read after every kStepsPerRead steps only
+    // (steps launched after the run stopped exit at once)
+    StepRecord* hist = nullptr;
+    if (hipMalloc(&hist, size_t(std::max(1, max_iter)) * sizeof(StepRecord)) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipMalloc of the step records failed");
+        dmp_tape_free(t);
+        return DMP_ENOMEM;
+    }
+    t->owned.push_back(hist);
+    constexpr int kStepsPerRead = 4;
     double* cur = P;
     double* nxt = Pw;
     if (!h.done) st = checkpoint(P, t->ckpt);
     if (stride == 1 && !h.done) cur = t->ckpt[0];
-    for (int k = 0; st == DMP_OK && !h.done && k < max_iter; ++k) {
-        // stride 1: X2_k and P_{k+1} are written straight into tape slots
-        double* x2k = X2;
-        if (stride == 1) {
-            st = slot(&x2k);
-            if (st == DMP_OK) st = slot(&nxt);
+    int launched = 0;
+    bool done = h.done != 0;
+    while (st == DMP_OK && !done && launched < max_iter) {
+        for (int c = 0; st == DMP_OK && c < kStepsPerRead && launched < max_iter; ++c, ++launched) {
+            // stride 1: X2_k and P_{k+1} are written straight into tape slots
+            double* x2k = X2;
+            if (stride == 1) {
+                st = slot(&x2k);
+                if (st == DMP_OK) st = slot(&nxt);
+                if (st != DMP_OK) break;
+                t->x2.push_back(x2k);
+            }
+            st = forward_iteration(x, cur, x2k, nxt, true, s);
             if (st != DMP_OK) break;
-            t->x2.push_back(x2k);
+            k_record_step<<<1, 64, 0, s>>>(x.st, hist);
+            if (hipGetLastError() != hipSuccess) {
+                set_error("launch of the step record failed");
+                st = DMP_EHIP;
+                break;
+            }
+            if (stride == 1) {
+                cur = nxt;
+                t->ckpt.push_back(cur);
+            } else {
+                std::swap(cur, nxt);
+                if ((launched + 1) % stride == 0) st = checkpoint(cur, t->ckpt);
+            }
         }
-        st = forward_iteration(x, cur, x2k, nxt, true, s);
         if (st != DMP_OK) break;
         if (hipMemcpyAsync(&h, x.st, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) {
@@ -603,26 +648,34 @@ int dmp_purify_fwd_tape(const double* H, int n, int nocc, double tol, int slices
             st = DMP_EHIP;
             break;
         }
-        t->c.push_back(h.c);
-        t->branch.push_back(h.branch);
-        t->t1.push_back(h.t1);
-        t->t2.push_back(h.t2);
-        t->clamped.push_back(h.clamped);
-        if (stride == 1) {
-            cur = nxt;
-            if (!h.done) t->ckpt.push_back(cur);
-        } else {
-            std::swap(cur, nxt);
-            if (!h.done && (k + 1) % stride == 0) st = checkpoint(cur, t->ckpt);
-        }
+        done = h.done != 0;
+    }
+    const int K = st == DMP_OK ? h.iters : 0;
+    std::vector<StepRecord> rec(size_t(std::max(K, 1)));
+    if (st == DMP_OK && K > 0 &&
+        (hipMemcpyAsync(rec.data(), hist, size_t(K) * sizeof(StepRecord), hipMemcpyDeviceToHost, s) != hipSuccess ||
+         hipStreamSynchronize(s) != hipSuccess)) {
+        set_error("readback of the step records failed");
+        st = DMP_EHIP;
     }
     if (st != DMP_OK) {
         dmp_tape_free(t);
         return st;
     }
-    t->K = int(t->c.size());
-    if (cur != P) {
-        if (hipMemcpyAsync(P, cur, size_t(n) * n * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+    for (int k = 0; k < K; ++k) {
+        t->c.push_back(rec[k].c);
+        t->branch.push_back(rec[k].branch);
+        t->t1.push_back(rec[k].t1);
+        t->t2.push_back(rec[k].t2);
+        t->clamped.push_back(rec[k].clamped);
+    }
+    t->K = K;
+    // steps launched past the stop left their slots unwritten: P_K is slot K
+    // (stride 1) or, ping-ponging from P, P for even K and Pw for odd K
+    double* last = stride == 1 ? (K > 0 ? t->ckpt[K] : P) : (K % 2 == 0 ? P : Pw);
+    if (stride == 1 && int(t->x2.size()) > K) t->x2.resize(K);
+    if (last != P) {
+        if (hipMemcpyAsync(P, last, size_t(n) * n * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) {
             set_error("copy of the result failed");
             dmp_tape_free(t);
