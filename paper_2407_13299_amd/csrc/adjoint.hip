@@ -160,13 +160,23 @@ MatDesc gemm_desc(const OzCtx& x, const uint8_t* pa, const int* ea, const uint8_
 
 // One forward iteration P_in -> (X2_out, P_out) with the purification
 // kernels; the coefficient is recomputed on the device from the traces.
+// The row maxima of X2 and of P_out come from the products' epilogues (into
+// x.mb and x.ma, each zeroed by the split before its product); p_maxima:
+// x.ma already holds those of P_in (the previous iteration's update), so
+// its split runs only the digit kernel.
 int forward_iteration(const OzCtx& x, const double* P_in, double* X2_out, double* P_out,
-                      bool finalize, hipStream_t s) {
-    DMP_CHECK(launch_split(split_of(x, P_in, false, x.ma, x.ea, x.pa, 0), x.S, x.kind, x.st, s));
+                      bool finalize, bool p_maxima, hipStream_t s) {
+    SplitDesc sp = split_of(x, P_in, false, x.ma, x.ea, x.pa, 0);
+    sp.clear = x.mb;
+    if (p_maxima)
+        DMP_CHECK(launch_split_digits(sp, x.S, x.kind, x.st, s));
+    else
+        DMP_CHECK(launch_split(sp, x.S, x.kind, x.st, s));
     GemmParams p{};
     p.tiles = x.tiles_up;
     p.one = gemm_desc(x, x.pa, x.ea, x.pa, x.ea, X2_out);
     p.one.P = P_in;
+    p.one.rowmax = x.mb;
     p.partials = x.partials;
     p.states = x.st;
     p.mode = EPI_SQUARE;
@@ -177,11 +187,14 @@ int forward_iteration(const OzCtx& x, const double* P_in, double* X2_out, double
     }
     DMP_CHECK(launch_ozgemm(x.S, x.kind, p, x.nt_up, s, x.rb));
     DMP_CHECK(launch_finalize_coef(x.pd, x.st, 1, s));
-    DMP_CHECK(launch_split(split_of(x, X2_out, false, x.mb, x.eb, x.pb, 0), x.S, x.kind, x.st, s));
+    SplitDesc sx = split_of(x, X2_out, false, x.mb, x.eb, x.pb, 0);
+    sx.clear = x.ma;
+    DMP_CHECK(launch_split_digits(sx, x.S, x.kind, x.st, s));
     p.one = gemm_desc(x, x.pb, x.eb, x.pa, x.ea, P_out);
     p.one.P = P_in;
     p.one.X2 = X2_out;
     p.one.H = x.H;
+    p.one.rowmax = x.ma;
     p.mode = EPI_UPDATE;
     DMP_CHECK(launch_ozgemm(x.S, x.kind, p, x.nt_up, s, x.rb));
     if (finalize) DMP_CHECK(launch_finalize_iter(x.pd, x.st, 1, s));
@@ -625,7 +638,7 @@ int dmp_purify_fwd_tape(const double* H, int n, int nocc, double tol, int slices
                 if (st != DMP_OK) break;
                 t->x2.push_back(x2k);
             }
-            st = forward_iteration(x, cur, x2k, nxt, true, s);
+            st = forward_iteration(x, cur, x2k, nxt, true, launched > 0, s);
             if (st != DMP_OK) break;
             k_record_step<<<1, 64, 0, s>>>(x.st, hist);
             if (hipGetLastError() != hipSuccess) {
@@ -777,7 +790,7 @@ int dmp_purify_bwd(const dmp_tape* t, const double* Pbar, double* Hbar, void* ws
             DMP_CHECK_HIP(hipMemcpyAsync(x.st, &fresh, sizeof(fresh), hipMemcpyHostToDevice, s));
             for (int j = start; j < end; ++j)
                 DMP_CHECK(forward_iteration(x, segP[j - start], segX[j - start], segP[j - start + 1],
-                                            false, s));
+                                            false, j > start, s));
         }
         for (int j = end - 1; j >= start; --j) {
             const double* P = stored ? t->ckpt[j] : segP[j - start];
