@@ -50,9 +50,15 @@
  *     GEMM entry points take no lock.  Calls that share a workspace must not
  *     overlap.
  *   - Purification runs with the same workspace, sizes, kind, slice count
- *     and method replay one recorded launch sequence (a hipGraph, kept per
- *     device for the life of the process, at most 16); the device state is
- *     read once after as many iterations as the previous such run needed.
+ *     and method replay recorded launch sequences (hipGraphs, kept per
+ *     device for the life of the process, at most 16): a repeated run is one
+ *     graph launch of as many iterations as the previous such run needed,
+ *     then one read of the device state.
+ *   - Environment switches, for measurements only (results are the same,
+ *     bit for bit, except for the tile height, which sets the order of the
+ *     trace sums): DMP_TAIL_SPLIT=0 keeps every product tile whole,
+ *     DMP_TILE_ROWS=64 or 128 forces the purification tile height,
+ *     DMP_NO_GRAPH=1 launches the iterations eagerly.
  */
 #ifndef DMP_H
 #define DMP_H
