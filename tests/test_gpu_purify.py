@@ -225,9 +225,10 @@ def test_graph_replays_equal_eager_launches(method, dims, monkeypatch):
 
 @pytest.mark.parametrize("method", ["canonical", "trs4"])
 def test_cached_graph_reused_across_inputs(method, monkeypatch):
-    """Calls that share a workspace replay one cached graph (the matrices'
-    pointers live in descriptors uploaded per call) and read the device state
-    once after the number of replays the previous call needed.  Two matrices
+    """Calls that share a workspace reuse cached graphs (the matrices'
+    pointers live in descriptors uploaded per call): a repeated call launches
+    one graph of as many iterations as the previous call needed, then reads
+    the device state, and continues with replays if it needs more.  Two matrices
     of the same size that need different iteration counts, purified in turn
     through one workspace (so the predicted count is too high, then too low),
     give the eager launches' results bit for bit; so does a run stopped by
